@@ -1,0 +1,69 @@
+"""Adaptive double-exponential (tanh-sinh) quadrature, written from its definition.
+
+The paper evaluates the error integral (eq. errorIntegral) with a tanh-sinh
+transformation followed by trapezoidal quadrature (Alg. 1 step 2, after
+Takahasi & Mori), refining until the relative error estimate falls below
+1e-3 and warning after 15 refinements (Sec. "Description of Program").
+
+Rule used here (the paper leaves the internals to Boost; reading):
+  x(u) = (a+b)/2 + (b-a)/2 * tanh(pi/2 sinh u)
+  w(u) = (b-a)/2 * (pi/2) cosh u / cosh^2(pi/2 sinh u)
+  I_l  = 2^-l * sum over u in 2^-l Z, |u| <= 3, of w(u) f(x(u))
+  Level 0 uses u = -3..3; level l >= 1 adds the odd multiples of 2^-l.
+  The tail beyond |u| = 3 has weight below 2e-12 (b-a), far under the target.
+  Stop at the first level l >= min_level with
+      |I_l - I_{l-1}| <= max(rel_tol |I_l|, abs_tol)
+  (this also accepts I_l == I_{l-1} == 0); if level max_level is reached
+  without that, return I_max_level flagged as not converged.  abs_tol is the
+  rounding-noise floor of the integrand times the interval length: an integrand
+  known only to within that floor cannot show a smaller relative change, and an
+  integral below it is negligible against any attainable error budget (reading).
+"""
+
+from dataclasses import dataclass
+
+import numpy as np
+
+U_MAX = 3
+
+
+@dataclass
+class QuadratureResult:
+    value: float
+    level: int
+    converged: bool
+    evaluations: int
+
+
+def level_nodes(level: int) -> np.ndarray:
+    """The abscissae u that are new at this refinement level."""
+    if level == 0:
+        return np.arange(-U_MAX, U_MAX + 1, dtype=np.float64)
+    step = 2.0 ** (-level)
+    odd = np.arange(1, U_MAX * 2 ** level, 2, dtype=np.float64) * step
+    return np.concatenate([-odd[::-1], odd])
+
+
+def tanh_sinh(f, a: float, b: float, rel_tol: float = 1e-3, max_level: int = 15,
+              min_level: int = 3, abs_tol: float = 0.0) -> QuadratureResult:
+    """Integral of the vectorised function f over [a, b] (a <= b)."""
+    if b == a:
+        return QuadratureResult(0.0, 0, True, 0)
+    center = 0.5 * (a + b)
+    radius = 0.5 * (b - a)
+    total = 0.0
+    previous = None
+    evaluations = 0
+    value = 0.0
+    for level in range(max_level + 1):
+        u = level_nodes(level)
+        s = 0.5 * np.pi * np.sinh(u)
+        x = center + radius * np.tanh(s)
+        w = radius * 0.5 * np.pi * np.cosh(u) / np.cosh(s) ** 2
+        total += float(np.sum(w * f(x)))
+        evaluations += u.size
+        value = total * 2.0 ** (-level)
+        if previous is not None and level >= min_level and abs(value - previous) <= max(rel_tol * abs(value), abs_tol):
+            return QuadratureResult(value, level, True, evaluations)
+        previous = value
+    return QuadratureResult(value, max_level, False, evaluations)
