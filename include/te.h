@@ -1,0 +1,191 @@
+/*
+ * te.h - C ABI of libtimeevolve: restarted Krylov evolution v(t) = exp(-iHt) v0 on one
+ * AMD Instinct MI355X (gfx950), with the a-posteriori error bound of
+ * M. Michel & S. Zell, "TimeEvolver: A Program for Time Evolution With Improved
+ * Error Bound", Comput. Phys. Commun. (2022).
+ *
+ * Problem statement (paper, Sec. "Time Evolution in a Generic Physical Quantum System",
+ * eq. vOfT; Alg. 1 input/output): given a Hermitian sparse d x d matrix H, a complex
+ * vector v0, a time t and a maximal error err_max, return an approximation of
+ * exp(-iHt) v0 whose 2-norm error is bounded by the integral of eq. errorIntegral,
+ * summed over restarts, up to roundoff (eq. numericalError).
+ *
+ * Conventions for every call
+ *  - Complex numbers are interleaved (re, im) doubles, i.e. te_c128 has the layout of
+ *    std::complex<double>, hipDoubleComplex and torch.complex128.
+ *  - "device" pointers are HIP device pointers on the current device; "host" pointers are
+ *    ordinary host memory.  Ownership never transfers unless stated.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued on it; calls
+ *    documented as synchronous return only after that work completed.
+ *  - Every call returns a te_status; on failure te_last_error() gives a thread-local
+ *    message and output buffers are left unspecified.  Calls never abort the process.
+ *  - All arithmetic is FP64 / complex FP64; indices are int32.
+ */
+#ifndef TE_H
+#define TE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct te_hamiltonian_s* te_hamiltonian; /* opaque; owns a device copy of the CSR */
+typedef struct {
+    double re, im;
+} te_c128;
+typedef int32_t te_status;
+
+enum {
+    TE_OK = 0,
+    TE_ERR_INVALID_ARG = 1,    /* null pointer, t<0, tol<=0, non-finite scalars, m<2, ... */
+    TE_ERR_INVALID_CSR = 2,    /* row_ptr not monotone / not 0..nnz, column out of range,
+                                  non-finite value, nnz >= 2^31 */
+    TE_ERR_NOT_HERMITIAN = 3,  /* only with TE_CHECK_HERMITIAN */
+    TE_ERR_UNSUPPORTED = 4,    /* m > TE_MAX_KRYLOV */
+    TE_ERR_OUT_OF_MEMORY = 5,
+    TE_ERR_DEVICE = 6,         /* a HIP runtime error; te_last_error() holds its text */
+    TE_ERR_STEP_UNDERFLOW = 7, /* the step search halved max_halvings times without success */
+    TE_ERR_NONFINITE = 8,      /* NaN/Inf met in v0 or during the iteration */
+    TE_ERR_CAPACITY = 9        /* batch / engine capacity or memory budget exceeded */
+};
+
+/* warning bits of te_result.warnings (they never change the status) */
+#define TE_WARN_NUMERICAL 1u  /* accumulated roundoff estimate d*||H||_1*eps exceeds the
+                                 accumulated analytic bound (Sec. "Pseudocode", third remark) */
+#define TE_WARN_QUADRATURE 2u /* an error integral did not meet its stopping test within
+                                 quad_max_level refinements (Sec. "Description of Program") */
+
+/* flags of te_hamiltonian_create */
+#define TE_PTR_DEVICE 1u      /* row_ptr/col_idx/values are device pointers (else host) */
+#define TE_CHECK_HERMITIAN 2u /* verify H == H^H on the device (needs sorted columns) */
+
+#define TE_MAX_KRYLOV 64 /* largest Krylov dimension m: the small eigenproblem runs in one
+                            64-lane wavefront */
+
+/* Tunable constants of the step-size search (Alg. 1 step 2).  te_default_options()
+ * fills: n_substeps=10, t_init=0.1, shrink=0.97, quad_rel_tol=1e-3, quad_max_level=15,
+ * quad_min_level=3, max_halvings=64. */
+typedef struct {
+    int32_t n_substeps;     /* N_SUBSTEPS of Alg. 1 */
+    double t_init;          /* first step-size guess (Alg. 1 line 1) */
+    double shrink;          /* later restarts start from shrink * previous step */
+    double quad_rel_tol;    /* relative stopping test of the error integral */
+    int32_t quad_max_level; /* refinements before TE_WARN_QUADRATURE */
+    int32_t quad_min_level; /* refinements always taken */
+    int32_t max_halvings;   /* cap of the halving loop (TE_ERR_STEP_UNDERFLOW) */
+    uint32_t flags;         /* reserved, must be 0 */
+} te_options;
+
+typedef struct {
+    int32_t steps;           /* restarts taken */
+    int32_t matvecs;         /* products H*x */
+    int32_t breakdown_dim;   /* Krylov dimension at a lucky breakdown, else 0 */
+    uint32_t warnings;       /* TE_WARN_* bits */
+    double err_bound;        /* ||v0|| * sum of per-step integrals of eq. errorIntegral */
+    double num_err_estimate; /* ||v0|| * accumulated d*||H||_1*2^-52 (eq. numericalError) */
+    double t_reached;        /* == t on success */
+} te_result;
+
+void te_default_options(te_options* opt);
+const char* te_status_string(te_status s);
+const char* te_last_error(void);
+
+/* ---------------------------------------------------------------------------------------
+ * Hamiltonian handle (paper: the Hermitian matrix H handed to the evolver, Sec.
+ * "Description of Program"; CSR is the sparse format of the problem statement).
+ *   dim, nnz     : matrix size and stored entries; 1 <= dim, 0 < nnz < 2^31.
+ *   row_ptr      : int32[dim+1], row_ptr[0] = 0, non-decreasing, row_ptr[dim] = nnz.
+ *   col_idx      : int32[nnz], 0 <= col < dim (sorted per row if TE_CHECK_HERMITIAN).
+ *   values       : te_c128[nnz], finite.
+ * The arrays are copied; the caller keeps ownership.  Validation runs on the device and
+ * returns TE_ERR_INVALID_CSR / TE_ERR_NOT_HERMITIAN.  Synchronous.  The 1-norm
+ * max_i sum_j |H_ij| (equal to the column-sum norm for Hermitian H) is computed here. */
+te_status te_hamiltonian_create(te_hamiltonian* out, int64_t dim, int64_t nnz,
+                                const int32_t* row_ptr, const int32_t* col_idx,
+                                const te_c128* values, uint32_t flags, void* stream);
+te_status te_hamiltonian_destroy(te_hamiltonian h); /* frees everything the handle owns */
+te_status te_hamiltonian_info(te_hamiltonian h, int64_t* dim, int64_t* nnz, double* norm1);
+
+/* Device bytes of the workspace that te_evolve keeps inside the handle for Krylov
+ * dimension m (Krylov basis m*dim complex, one work vector, reduction partials, state). */
+size_t te_workspace_bytes(int64_t dim, int32_t m);
+
+/* Optional allocator hook for device memory that the library allocates (workspaces,
+ * handle copies).  NULL restores hipMalloc/hipFree.  Not thread-safe against running
+ * calls; set it once at start-up. */
+typedef void* (*te_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*te_free_fn)(void* ptr, void* ctx);
+te_status te_set_allocator(te_alloc_fn alloc, te_free_fn free_fn, void* ctx);
+
+/* ---------------------------------------------------------------------------------------
+ * te_evolve: Alg. 1 ("Krylov-method") end to end on the device.
+ *   v0     : device, dim complex; need not be normalised (the result and the bound scale
+ *            with ||v0||, the method itself runs on v0/||v0||).
+ *   v_out  : device, dim complex; may equal v0.
+ *   t >= 0, tol > 0 (err_max, the bound on the 2-norm of the final error), finite.
+ *   m      : Krylov dimension, 2 <= m <= TE_MAX_KRYLOV; clamped to dim.
+ *   opt    : NULL for defaults.   res : host, may be NULL.
+ * Every restart (Arnoldi steps, diagonalisation of the small Hessenberg matrix, error
+ * integral, step-size search, recombination) runs on the device; the host only enqueues
+ * restarts ahead of the device and stops once the device reports completion.
+ * t == 0 copies v0; ||v0|| == 0 returns zeros with a zero bound.  Synchronous.
+ * Calls on one handle are serialised (the handle holds one workspace). */
+te_status te_evolve(te_hamiltonian h, const te_c128* v0, te_c128* v_out, double t, double tol,
+                    int32_t m, const te_options* opt, te_result* res, void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Component entry points: each runs one step of the hot path with the same kernels that
+ * te_evolve uses, for testing and for callers that assemble their own loop.
+ *
+ * te_spmv (eq. arnoldi, first line: w_j = H v_j, fused with the projection <v_j, w_j>):
+ *   x, y: device, dim complex, must not alias.  xhy: host, receives x^H y (may be NULL).
+ *   Synchronous. */
+te_status te_spmv(te_hamiltonian h, const te_c128* x, te_c128* y, te_c128* xhy, void* stream);
+
+/* te_arnoldi (Alg. 1 step 1, with full re-orthogonalisation): builds the Krylov basis of
+ * u (device, dim, assumed normalised) for Lanczos on H.
+ *   V      : device, m*dim complex, column-major (column i at V + i*dim), receives the
+ *            orthonormal basis v_1..v_k (columns >= k are unspecified).
+ *   alpha  : host double[m], diagonal of the real symmetric tridiagonal J = V^H H V.
+ *   beta   : host double[m], beta[i] = ||residual|| after step i (off-diagonal J_{i+1,i}
+ *            for i < k-1; beta[k-1] = h, the h_{k+1,k} of eq. errorIntegral).
+ *   k_out  : host, Krylov dimension reached (< m after a lucky breakdown, no < tol_rate).
+ *   Synchronous. */
+te_status te_arnoldi(te_hamiltonian h, const te_c128* u, int32_t m, double tol_rate,
+                     te_c128* V, double* alpha, double* beta, int32_t* k_out, void* stream);
+
+/* te_tridiag_eig (Sec. "Pseudocode", first remark: diagonalise H_m once per restart):
+ * J = Q diag(lambda) Q^T for the k x k real symmetric tridiagonal with diagonal alpha[k]
+ * and off-diagonal beta[k-1].  Host arrays in/out; Q is column-major k*k (column n is the
+ * eigenvector of lambda[n]); eigenvalues are not sorted.  Runs on the device in one
+ * wavefront.  1 <= k <= TE_MAX_KRYLOV.  Synchronous. */
+te_status te_tridiag_eig(int32_t k, const double* alpha, const double* beta, double* lambda,
+                         double* Q, void* stream);
+
+/* te_error_integral (eq. errorIntegral on [a, b]): integral of
+ * f(tau) = h |sum_n coef[n] exp(-i lambda[n] tau)| by the device tanh-sinh rule.
+ *   lambda, coef: host double[k]; value/level/converged: host outputs.  Synchronous. */
+te_status te_error_integral(int32_t k, const double* lambda, const double* coef, double h,
+                            double a, double b, const te_options* opt, double* value,
+                            int32_t* level, int32_t* converged, void* stream);
+
+/* te_step_search (Alg. 1 step 2 and the coefficients omega of its last line): from the
+ * tridiagonal (alpha[k], beta[k-1]), residual norm h and the rate tol_rate = err_max/t
+ * (eq. errorRate), the largest admissible step tau <= t_rem (eq. stepSize) with its
+ * integral err, and omega = exp(-iJ tau) e_1 (host te_c128[k]).
+ *   first   : nonzero on the first restart (doubling from t_init), else tau_prev is used.
+ *   breakdown: nonzero when the Krylov space is invariant (tau = t_rem).
+ *   warnings: host, TE_WARN_QUADRATURE if an integral did not converge.
+ * Returns TE_ERR_STEP_UNDERFLOW when no admissible step is found.  Synchronous. */
+te_status te_step_search(int32_t k, const double* alpha, const double* beta, double h,
+                         double tol_rate, double t_rem, int32_t first, double tau_prev,
+                         int32_t breakdown, const te_options* opt, double* tau, double* err,
+                         te_c128* omega, uint32_t* warnings, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TE_H */

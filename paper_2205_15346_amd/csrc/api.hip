@@ -1,0 +1,638 @@
+// Host side of the C ABI declared in include/te.h.
+//
+// te_evolve enqueues, per restart, the 2m row-parallel kernels of one Krylov build, the
+// one-block step kernel and the recombination (captured once as a hipGraph per workspace).
+// All decisions are taken on the device; the host keeps one restart queued ahead of the
+// one that is running and stops launching when the step kernel has raised its done flag
+// (written to mapped pinned memory).  Restarts launched after completion are no-ops.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "te_internal.h"
+
+using namespace te;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+te_alloc_fn g_alloc = nullptr;
+te_free_fn g_free = nullptr;
+void* g_alloc_ctx = nullptr;
+
+te_status fail(te_status s, const std::string& msg) {
+    g_last_error = msg;
+    return s;
+}
+
+#define TE_HIP(call)                                                                                   \
+    do {                                                                                               \
+        hipError_t e_ = (call);                                                                        \
+        if (e_ != hipSuccess)                                                                          \
+            return fail(e_ == hipErrorOutOfMemory ? TE_ERR_OUT_OF_MEMORY : TE_ERR_DEVICE,              \
+                        std::string(#call) + ": " + hipGetErrorString(e_));                            \
+    } while (0)
+
+void* dev_alloc(size_t bytes) {
+    if (bytes == 0) bytes = 1;
+    if (g_alloc) return g_alloc(bytes, g_alloc_ctx);
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    return p;
+}
+
+void dev_free(void* p) {
+    if (!p) return;
+    if (g_free) g_free(p, g_alloc_ctx);
+    else (void)hipFree(p);
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace
+
+// ------------------------------------------------------------------------- workspace
+namespace te {
+
+struct Workspace {
+    int dim = 0, m = 0;
+    int64_t ld = 0;
+    Tiling tl{};
+    char* base = nullptr;  // one device allocation
+    double2* V = nullptr;
+    double2* y = nullptr;
+    RedBuf rb{};
+    DevState* st = nullptr;
+    int* host_flag = nullptr;  // mapped pinned
+    int* host_flag_dev = nullptr;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    size_t bytes = 0;
+
+    static size_t layout(int dim, int m, const Tiling& tl, size_t* off_y, size_t* off_part, size_t* off_gpart,
+                         size_t* off_cnt, size_t* off_st) {
+        const size_t ld = align_up((size_t)dim, 64);
+        size_t o = 0;
+        o += (size_t)m * ld * sizeof(double2);
+        *off_y = o;
+        o += ld * sizeof(double2);
+        o = align_up(o, 256);
+        *off_part = o;
+        o += (size_t)kMaxVals * tl.n_tiles * sizeof(double2);
+        o = align_up(o, 256);
+        *off_gpart = o;
+        o += (size_t)kMaxVals * tl.n_groups * sizeof(double2);
+        o = align_up(o, 256);
+        *off_cnt = o;
+        o += (size_t)(tl.n_groups + 1) * sizeof(unsigned);
+        o = align_up(o, 256);
+        *off_st = o;
+        o += sizeof(DevState);
+        return align_up(o, 256);
+    }
+
+    ~Workspace() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        if (host_flag) (void)hipHostFree(host_flag);
+        dev_free(base);
+    }
+};
+
+}  // namespace te
+
+struct te_hamiltonian_s {
+    Csr csr{};
+    int* row_ptr = nullptr;
+    int* col = nullptr;
+    double2* val = nullptr;
+    double norm1 = 0.0;
+    std::mutex mu;
+    Workspace* ws = nullptr;
+    ~te_hamiltonian_s() {
+        delete ws;
+        dev_free(row_ptr);
+        dev_free(col);
+        dev_free(val);
+    }
+};
+
+namespace {
+
+te_status make_workspace(te_hamiltonian h, int m, Workspace** out) {
+    auto* w = new (std::nothrow) Workspace();
+    if (!w) return fail(TE_ERR_OUT_OF_MEMORY, "host allocation failed");
+    w->dim = h->csr.dim;
+    w->m = m;
+    w->ld = (int64_t)align_up((size_t)w->dim, 64);
+    w->tl = choose_tiling(w->dim);
+    size_t oy, op, og, oc, os;
+    w->bytes = Workspace::layout(w->dim, m, w->tl, &oy, &op, &og, &oc, &os);
+    w->base = (char*)dev_alloc(w->bytes);
+    if (!w->base) {
+        delete w;
+        return fail(TE_ERR_OUT_OF_MEMORY, "workspace allocation of " + std::to_string(w->bytes) + " bytes failed");
+    }
+    w->V = (double2*)w->base;
+    w->y = (double2*)(w->base + oy);
+    w->rb.part = (double2*)(w->base + op);
+    w->rb.gpart = (double2*)(w->base + og);
+    w->rb.gcnt = (unsigned*)(w->base + oc);
+    w->rb.fcnt = w->rb.gcnt + w->tl.n_groups;
+    w->rb.n_tiles = w->tl.n_tiles;
+    w->rb.n_groups = w->tl.n_groups;
+    w->st = (DevState*)(w->base + os);
+    te_status rc = TE_OK;
+    auto chk = [&](hipError_t e, const char* what) {
+        if (e != hipSuccess && rc == TE_OK) rc = fail(TE_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    };
+    chk(hipMemset(w->base + oc, 0, (size_t)(w->tl.n_groups + 1) * sizeof(unsigned)), "hipMemset");
+    chk(hipMemset(w->st, 0, sizeof(DevState)), "hipMemset");
+    chk(hipHostMalloc((void**)&w->host_flag, 64, hipHostMallocMapped | hipHostMallocCoherent), "hipHostMalloc");
+    if (rc == TE_OK) chk(hipHostGetDevicePointer((void**)&w->host_flag_dev, w->host_flag, 0), "hipHostGetDevicePointer");
+    chk(hipStreamCreateWithFlags(&w->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
+    chk(hipEventCreateWithFlags(&w->ev[0], hipEventDisableTiming), "hipEventCreate");
+    chk(hipEventCreateWithFlags(&w->ev[1], hipEventDisableTiming), "hipEventCreate");
+    chk(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    if (rc != TE_OK) {
+        delete w;
+        return rc;
+    }
+    *out = w;
+    return TE_OK;
+}
+
+// enqueue one restart (2m kernels + step + combine) on stream s
+hipError_t enqueue_restart(te_hamiltonian h, Workspace* w, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    for (int j = 0; j < w->m && e == hipSuccess; ++j) {
+        e = launch_project(w->tl, h->csr, w->V, w->ld, j, w->y, w->st, w->rb, s);
+        if (e == hipSuccess) e = launch_update(w->tl, w->V, w->ld, w->dim, j, w->y, w->st, w->rb, s);
+    }
+    if (e == hipSuccess) e = launch_step(w->st, w->host_flag_dev, s);
+    if (e == hipSuccess) e = launch_combine(w->tl, w->V, w->ld, w->dim, w->st, s);
+    return e;
+}
+
+bool graphs_enabled() {
+    const char* v = std::getenv("TE_NO_GRAPH");
+    return !(v && v[0] == '1');
+}
+
+te_status ensure_graph(te_hamiltonian h, Workspace* w) {
+    if (w->exec || !graphs_enabled()) return TE_OK;
+    TE_HIP(hipStreamBeginCapture(w->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t le = enqueue_restart(h, w, w->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t ce = hipStreamEndCapture(w->cap_stream, &g);
+    if (le != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(TE_ERR_DEVICE, std::string("kernel launch during capture: ") + hipGetErrorString(le));
+    }
+    if (ce != hipSuccess) return fail(TE_ERR_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
+    w->graph = g;
+    TE_HIP(hipGraphInstantiate(&w->exec, g, nullptr, nullptr, 0));
+    return TE_OK;
+}
+
+te_status get_workspace(te_hamiltonian h, int m, Workspace** out) {
+    if (h->ws && h->ws->m == m) {
+        *out = h->ws;
+        return TE_OK;
+    }
+    delete h->ws;
+    h->ws = nullptr;
+    Workspace* w = nullptr;
+    te_status rc = make_workspace(h, m, &w);
+    if (rc != TE_OK) return rc;
+    h->ws = w;
+    rc = ensure_graph(h, w);
+    if (rc != TE_OK) return rc;
+    *out = w;
+    return TE_OK;
+}
+
+Problem make_problem(te_hamiltonian h, const te_options& o, double t, double tol, int m) {
+    Problem p{};
+    p.t = t;
+    p.tol_rate = tol / t;
+    p.numerr_per_step = (double)h->csr.dim * h->norm1 * std::ldexp(1.0, -52);
+    p.t_init = o.t_init;
+    p.shrink = o.shrink;
+    p.quad_rel_tol = o.quad_rel_tol;
+    p.m = m;
+    p.dim = h->csr.dim;
+    p.n_substeps = o.n_substeps;
+    p.quad_max_level = o.quad_max_level;
+    p.quad_min_level = o.quad_min_level;
+    p.max_halvings = o.max_halvings;
+    return p;
+}
+
+te_status check_options(const te_options& o) {
+    if (o.n_substeps < 1 || !(o.t_init > 0.0) || !std::isfinite(o.t_init) || !(o.shrink > 0.0) || !(o.shrink <= 1.0) ||
+        !(o.quad_rel_tol > 0.0) || o.quad_max_level < 0 || o.quad_max_level > 20 || o.quad_min_level < 0 ||
+        o.max_halvings < 0 || o.flags != 0)
+        return fail(TE_ERR_INVALID_ARG, "invalid te_options");
+    return TE_OK;
+}
+
+}  // namespace
+
+// ============================================================================== C ABI
+extern "C" {
+
+void te_default_options(te_options* o) {
+    if (!o) return;
+    o->n_substeps = 10;
+    o->t_init = 0.1;
+    o->shrink = 0.97;
+    o->quad_rel_tol = 1e-3;
+    o->quad_max_level = 15;
+    o->quad_min_level = 3;
+    o->max_halvings = 64;
+    o->flags = 0;
+}
+
+const char* te_status_string(te_status s) {
+    switch (s) {
+        case TE_OK: return "ok";
+        case TE_ERR_INVALID_ARG: return "invalid argument";
+        case TE_ERR_INVALID_CSR: return "invalid CSR matrix";
+        case TE_ERR_NOT_HERMITIAN: return "matrix is not Hermitian";
+        case TE_ERR_UNSUPPORTED: return "unsupported parameter";
+        case TE_ERR_OUT_OF_MEMORY: return "out of device memory";
+        case TE_ERR_DEVICE: return "HIP device error";
+        case TE_ERR_STEP_UNDERFLOW: return "step-size search underflow";
+        case TE_ERR_NONFINITE: return "non-finite value";
+        case TE_ERR_CAPACITY: return "capacity exceeded";
+        default: return "unknown status";
+    }
+}
+
+const char* te_last_error(void) { return g_last_error.c_str(); }
+
+te_status te_set_allocator(te_alloc_fn alloc, te_free_fn free_fn, void* ctx) {
+    if ((alloc == nullptr) != (free_fn == nullptr)) return fail(TE_ERR_INVALID_ARG, "alloc and free must be set together");
+    g_alloc = alloc;
+    g_free = free_fn;
+    g_alloc_ctx = ctx;
+    return TE_OK;
+}
+
+size_t te_workspace_bytes(int64_t dim, int32_t m) {
+    if (dim < 1 || dim >= (int64_t)1 << 31 || m < 1) return 0;
+    const int mm = (int)std::min<int64_t>(m, dim);
+    size_t a, b, c, d, e;
+    return Workspace::layout((int)dim, mm, choose_tiling((int)dim), &a, &b, &c, &d, &e);
+}
+
+te_status te_hamiltonian_create(te_hamiltonian* out, int64_t dim, int64_t nnz, const int32_t* row_ptr,
+                                const int32_t* col_idx, const te_c128* values, uint32_t flags, void* stream) {
+    if (!out || !row_ptr || !col_idx || !values) return fail(TE_ERR_INVALID_ARG, "null pointer");
+    *out = nullptr;
+    if (dim < 1 || dim >= ((int64_t)1 << 31) - 1) return fail(TE_ERR_INVALID_ARG, "dim out of range");
+    if (nnz < 1 || nnz >= ((int64_t)1 << 31)) return fail(TE_ERR_INVALID_CSR, "nnz out of range (1..2^31-1)");
+    if (flags & ~(TE_PTR_DEVICE | TE_CHECK_HERMITIAN)) return fail(TE_ERR_INVALID_ARG, "unknown flags");
+    hipStream_t s = (hipStream_t)stream;
+    auto* h = new (std::nothrow) te_hamiltonian_s();
+    if (!h) return fail(TE_ERR_OUT_OF_MEMORY, "host allocation failed");
+    h->row_ptr = (int*)dev_alloc((dim + 1) * sizeof(int));
+    h->col = (int*)dev_alloc(nnz * sizeof(int));
+    h->val = (double2*)dev_alloc(nnz * sizeof(double2));
+    double* rowsum = (double*)dev_alloc(dim * sizeof(double) + 64);
+    int* err = (int*)dev_alloc(64);
+    if (!h->row_ptr || !h->col || !h->val || !rowsum || !err) {
+        dev_free(rowsum);
+        dev_free(err);
+        delete h;
+        return fail(TE_ERR_OUT_OF_MEMORY, "device allocation for the matrix failed");
+    }
+    const hipMemcpyKind kind = (flags & TE_PTR_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    te_status rc = TE_OK;
+    int herr = 0;
+    double norm1 = 0.0;
+    auto chk = [&](hipError_t e, const char* what) {
+        if (e != hipSuccess && rc == TE_OK)
+            rc = fail(e == hipErrorOutOfMemory ? TE_ERR_OUT_OF_MEMORY : TE_ERR_DEVICE,
+                      std::string(what) + ": " + hipGetErrorString(e));
+    };
+    chk(hipMemcpyAsync(h->row_ptr, row_ptr, (dim + 1) * sizeof(int), kind, s), "copy row_ptr");
+    chk(hipMemcpyAsync(h->col, col_idx, nnz * sizeof(int), kind, s), "copy col_idx");
+    chk(hipMemcpyAsync(h->val, values, nnz * sizeof(double2), kind, s), "copy values");
+    chk(hipMemsetAsync(err, 0, sizeof(int), s), "hipMemsetAsync");
+    h->csr.row_ptr = h->row_ptr;
+    h->csr.col = h->col;
+    h->csr.val = h->val;
+    h->csr.dim = (int)dim;
+    h->csr.nnz = nnz;
+    if (rc == TE_OK) chk(launch_validate(h->csr, (flags & TE_CHECK_HERMITIAN) ? 1 : 0, err, rowsum, s), "validate");
+    if (rc == TE_OK) chk(launch_norm1(rowsum, (int)dim, rowsum + dim, s), "norm1");
+    if (rc == TE_OK) chk(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s), "copy status");
+    if (rc == TE_OK) chk(hipMemcpyAsync(&norm1, rowsum + dim, sizeof(double), hipMemcpyDeviceToHost, s), "copy norm");
+    if (rc == TE_OK) chk(hipStreamSynchronize(s), "hipStreamSynchronize");
+    dev_free(rowsum);
+    dev_free(err);
+    if (rc == TE_OK && (herr & (1 | 2 | 4 | 8)))
+        rc = fail(TE_ERR_INVALID_CSR, "invalid CSR (code " + std::to_string(herr) + ": 1 structure, 2 column range, "
+                                      "4 non-finite value, 8 unsorted columns)");
+    if (rc == TE_OK && (herr & 16)) rc = fail(TE_ERR_NOT_HERMITIAN, "H differs from its conjugate transpose");
+    if (rc != TE_OK) {
+        delete h;
+        return rc;
+    }
+    h->norm1 = norm1;
+    *out = h;
+    return TE_OK;
+}
+
+te_status te_hamiltonian_destroy(te_hamiltonian h) {
+    if (!h) return fail(TE_ERR_INVALID_ARG, "null handle");
+    (void)hipDeviceSynchronize();
+    delete h;
+    return TE_OK;
+}
+
+te_status te_hamiltonian_info(te_hamiltonian h, int64_t* dim, int64_t* nnz, double* norm1) {
+    if (!h) return fail(TE_ERR_INVALID_ARG, "null handle");
+    if (dim) *dim = h->csr.dim;
+    if (nnz) *nnz = h->csr.nnz;
+    if (norm1) *norm1 = h->norm1;
+    return TE_OK;
+}
+
+te_status te_evolve(te_hamiltonian h, const te_c128* v0, te_c128* v_out, double t, double tol, int32_t m,
+                    const te_options* opt, te_result* res, void* stream) {
+    if (!h || !v0 || !v_out) return fail(TE_ERR_INVALID_ARG, "null pointer");
+    if (!std::isfinite(t) || t < 0.0) return fail(TE_ERR_INVALID_ARG, "t must be finite and >= 0");
+    if (!std::isfinite(tol) || !(tol > 0.0)) return fail(TE_ERR_INVALID_ARG, "tol must be finite and > 0");
+    if (m < 2) return fail(TE_ERR_INVALID_ARG, "m must be >= 2");
+    if (m > TE_MAX_KRYLOV) return fail(TE_ERR_UNSUPPORTED, "m > TE_MAX_KRYLOV");
+    te_options o;
+    te_default_options(&o);
+    if (opt) o = *opt;
+    te_status rc = check_options(o);
+    if (rc != TE_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const int dim = h->csr.dim;
+    std::lock_guard<std::mutex> lock(h->mu);
+    if (res) std::memset(res, 0, sizeof(*res));
+    if (t == 0.0) {
+        if (v_out != v0) TE_HIP(hipMemcpyAsync(v_out, v0, (size_t)dim * sizeof(te_c128), hipMemcpyDeviceToDevice, s));
+        TE_HIP(hipStreamSynchronize(s));
+        return TE_OK;
+    }
+    const int mm = std::min(m, dim);
+    Workspace* w = nullptr;
+    rc = get_workspace(h, mm, &w);
+    if (rc != TE_OK) return rc;
+    const Problem prob = make_problem(h, o, t, tol, mm);
+    *(volatile int*)w->host_flag = 0;
+    TE_HIP(launch_init(w->tl, (const double2*)v0, w->V, dim, w->st, w->rb, prob, s));
+    const long max_restarts = 100000000L;
+    long r = 0;
+    for (;; ++r) {
+        if (w->exec) TE_HIP(hipGraphLaunch(w->exec, s));
+        else TE_HIP(enqueue_restart(h, w, s));
+        TE_HIP(hipEventRecord(w->ev[r & 1], s));
+        if (r >= 1) {
+            TE_HIP(hipEventSynchronize(w->ev[(r - 1) & 1]));
+            if (*(volatile int*)w->host_flag) break;
+        }
+        if (r >= max_restarts) return fail(TE_ERR_DEVICE, "restart limit reached");
+    }
+    TE_HIP(launch_output(w->tl, w->V, (double2*)v_out, dim, w->st, s));
+    DevState hs;
+    TE_HIP(hipMemcpyAsync(&hs, w->st, offsetof(DevState, alpha), hipMemcpyDeviceToHost, s));
+    TE_HIP(hipStreamSynchronize(s));
+    if (res) {
+        res->steps = hs.steps;
+        res->matvecs = hs.matvecs;
+        res->breakdown_dim = hs.breakdown_dim;
+        res->warnings = (uint32_t)hs.warnings;
+        res->err_bound = hs.beta0 * hs.err_acc;
+        res->num_err_estimate = hs.beta0 * hs.num_acc;
+        res->t_reached = hs.t_now;
+    }
+    if (hs.status != TE_OK) {
+        if (hs.status == TE_ERR_STEP_UNDERFLOW)
+            return fail(hs.status, "no admissible step after max_halvings halvings (t_now=" + std::to_string(hs.t_now) + ")");
+        if (hs.status == TE_ERR_NONFINITE) return fail(hs.status, "non-finite value in v0 or during the iteration");
+        return fail(hs.status, "device-side failure (eigensolver did not converge)");
+    }
+    if (hs.beta0 == 0.0 && res) res->t_reached = t;
+    return TE_OK;
+}
+
+// ------------------------------------------------------------------ component entry points
+te_status te_spmv(te_hamiltonian h, const te_c128* x, te_c128* y, te_c128* xhy, void* stream) {
+    if (!h || !x || !y) return fail(TE_ERR_INVALID_ARG, "null pointer");
+    if ((const void*)x == (void*)y) return fail(TE_ERR_INVALID_ARG, "x and y must not alias");
+    hipStream_t s = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lock(h->mu);
+    Workspace* w = nullptr;
+    te_status rc = get_workspace(h, h->ws ? h->ws->m : std::min(2, h->csr.dim), &w);
+    if (rc != TE_OK) return rc;
+    TE_HIP(launch_spmv_only(w->tl, h->csr, (const double2*)x, (double2*)y, w->st, w->rb, s));
+    double2 dot;
+    TE_HIP(hipMemcpyAsync(&dot, &w->st->ceff[0], sizeof(double2), hipMemcpyDeviceToHost, s));
+    TE_HIP(hipStreamSynchronize(s));
+    if (xhy) {
+        xhy->re = dot.x;
+        xhy->im = dot.y;
+    }
+    return TE_OK;
+}
+
+}  // extern "C"
+
+namespace te {
+hipError_t launch_scale_columns(const double2* src, double2* dst, int64_t ld, int dim, int k, const DevState* st,
+                                hipStream_t s);
+}
+
+extern "C" {
+
+te_status te_arnoldi(te_hamiltonian h, const te_c128* u, int32_t m, double tol_rate, te_c128* V, double* alpha,
+                     double* beta, int32_t* k_out, void* stream) {
+    if (!h || !u || !V || !alpha || !beta || !k_out) return fail(TE_ERR_INVALID_ARG, "null pointer");
+    if (m < 1 || m > TE_MAX_KRYLOV) return fail(TE_ERR_INVALID_ARG, "m out of range");
+    if (!(tol_rate >= 0.0) || !std::isfinite(tol_rate)) return fail(TE_ERR_INVALID_ARG, "tol_rate must be >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lock(h->mu);
+    const int dim = h->csr.dim;
+    const int mm = std::min<int>(m, dim);
+    Workspace* w = nullptr;
+    te_status rc = get_workspace(h, mm, &w);
+    if (rc != TE_OK) return rc;
+    te_options o;
+    te_default_options(&o);
+    Problem prob = make_problem(h, o, 1.0, 1.0, mm);
+    prob.tol_rate = tol_rate;
+    TE_HIP(launch_init(w->tl, (const double2*)u, w->V, dim, w->st, w->rb, prob, s));
+    for (int j = 0; j < mm; ++j) {
+        TE_HIP(launch_project(w->tl, h->csr, w->V, w->ld, j, w->y, w->st, w->rb, s));
+        TE_HIP(launch_update(w->tl, w->V, w->ld, dim, j, w->y, w->st, w->rb, s));
+    }
+    DevState hs;
+    TE_HIP(hipMemcpyAsync(&hs, w->st, offsetof(DevState, ceff), hipMemcpyDeviceToHost, s));
+    TE_HIP(hipStreamSynchronize(s));
+    if (hs.status != TE_OK) return fail(hs.status, "non-finite value during the Krylov build");
+    if (hs.done) return fail(TE_ERR_INVALID_ARG, "start vector has zero norm");
+    const int k = hs.k_limit;
+    TE_HIP(launch_scale_columns(w->V, (double2*)V, w->ld, dim, k, w->st, s));
+    TE_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < mm; ++i) {
+        alpha[i] = (i < k) ? hs.alpha[i] : 0.0;
+        beta[i] = (i < k) ? hs.beta[i] : 0.0;
+    }
+    *k_out = k;
+    return TE_OK;
+}
+
+te_status te_tridiag_eig(int32_t k, const double* alpha, const double* beta, double* lambda, double* Q, void* stream) {
+    if (!alpha || !lambda || !Q || (k > 1 && !beta)) return fail(TE_ERR_INVALID_ARG, "null pointer");
+    if (k < 1 || k > TE_MAX_KRYLOV) return fail(TE_ERR_INVALID_ARG, "k out of range");
+    for (int i = 0; i < k; ++i)
+        if (!std::isfinite(alpha[i]) || (i < k - 1 && !std::isfinite(beta[i])))
+            return fail(TE_ERR_NONFINITE, "non-finite tridiagonal entry");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t n = (size_t)k;
+    double* d = (double*)dev_alloc((4 * n + n * n) * sizeof(double) + 64);
+    if (!d) return fail(TE_ERR_OUT_OF_MEMORY, "device allocation failed");
+    double *da = d, *db = d + n, *dl = d + 2 * n, *dq = d + 4 * n;
+    int* dst = (int*)(d + 3 * n);
+    te_status rc = TE_OK;
+    int status = 0;
+    auto chk = [&](hipError_t e, const char* what) {
+        if (e != hipSuccess && rc == TE_OK) rc = fail(TE_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    };
+    chk(hipMemcpyAsync(da, alpha, n * sizeof(double), hipMemcpyHostToDevice, s), "copy");
+    if (k > 1) chk(hipMemcpyAsync(db, beta, (n - 1) * sizeof(double), hipMemcpyHostToDevice, s), "copy");
+    if (rc == TE_OK) chk(launch_eig_only(k, da, db, dl, dq, dst, s), "launch");
+    if (rc == TE_OK) chk(hipMemcpyAsync(lambda, dl, n * sizeof(double), hipMemcpyDeviceToHost, s), "copy");
+    if (rc == TE_OK) chk(hipMemcpyAsync(Q, dq, n * n * sizeof(double), hipMemcpyDeviceToHost, s), "copy");
+    if (rc == TE_OK) chk(hipMemcpyAsync(&status, dst, sizeof(int), hipMemcpyDeviceToHost, s), "copy");
+    if (rc == TE_OK) chk(hipStreamSynchronize(s), "sync");
+    dev_free(d);
+    if (rc == TE_OK && status) rc = fail(TE_ERR_DEVICE, "QL iteration did not converge");
+    return rc;
+}
+
+te_status te_error_integral(int32_t k, const double* lambda, const double* coef, double h, double a, double b,
+                            const te_options* opt, double* value, int32_t* level, int32_t* converged, void* stream) {
+    if (!lambda || !coef || !value) return fail(TE_ERR_INVALID_ARG, "null pointer");
+    if (k < 1 || k > TE_MAX_KRYLOV) return fail(TE_ERR_INVALID_ARG, "k out of range");
+    if (!std::isfinite(a) || !std::isfinite(b) || b < a || !std::isfinite(h) || h < 0.0)
+        return fail(TE_ERR_INVALID_ARG, "need finite a <= b and h >= 0");
+    te_options o;
+    te_default_options(&o);
+    if (opt) o = *opt;
+    te_status rc = check_options(o);
+    if (rc != TE_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    Problem p{};
+    p.quad_rel_tol = o.quad_rel_tol;
+    p.quad_max_level = o.quad_max_level;
+    p.quad_min_level = o.quad_min_level;
+    const size_t n = (size_t)k;
+    double* d = (double*)dev_alloc((2 * n + 4) * sizeof(double));
+    if (!d) return fail(TE_ERR_OUT_OF_MEMORY, "device allocation failed");
+    double out[3] = {0, 0, 0};
+    auto chk = [&](hipError_t e, const char* what) {
+        if (e != hipSuccess && rc == TE_OK) rc = fail(TE_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    };
+    chk(hipMemcpyAsync(d, lambda, n * sizeof(double), hipMemcpyHostToDevice, s), "copy");
+    chk(hipMemcpyAsync(d + n, coef, n * sizeof(double), hipMemcpyHostToDevice, s), "copy");
+    if (rc == TE_OK) chk(launch_integral_only(k, d, d + n, h, a, b, p, d + 2 * n, s), "launch");
+    if (rc == TE_OK) chk(hipMemcpyAsync(out, d + 2 * n, 3 * sizeof(double), hipMemcpyDeviceToHost, s), "copy");
+    if (rc == TE_OK) chk(hipStreamSynchronize(s), "sync");
+    dev_free(d);
+    if (rc != TE_OK) return rc;
+    *value = out[0];
+    if (level) *level = (int32_t)out[1];
+    if (converged) *converged = (int32_t)out[2];
+    return TE_OK;
+}
+
+te_status te_step_search(int32_t k, const double* alpha, const double* beta, double h, double tol_rate, double t_rem,
+                         int32_t first, double tau_prev, int32_t breakdown, const te_options* opt, double* tau,
+                         double* err, te_c128* omega, uint32_t* warnings, void* stream) {
+    if (!alpha || !tau || !err || !omega || (k > 1 && !beta)) return fail(TE_ERR_INVALID_ARG, "null pointer");
+    if (k < 1 || k > TE_MAX_KRYLOV) return fail(TE_ERR_INVALID_ARG, "k out of range");
+    if (!(t_rem > 0.0) || !std::isfinite(t_rem) || !(tol_rate > 0.0) || !std::isfinite(tol_rate) || !(h >= 0.0) ||
+        !std::isfinite(h) || (!first && !(tau_prev > 0.0)))
+        return fail(TE_ERR_INVALID_ARG, "invalid scalar argument");
+    te_options o;
+    te_default_options(&o);
+    if (opt) o = *opt;
+    te_status rc = check_options(o);
+    if (rc != TE_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    DevState* hs = new (std::nothrow) DevState();
+    if (!hs) return fail(TE_ERR_OUT_OF_MEMORY, "host allocation failed");
+    std::memset(hs, 0, sizeof(DevState));
+    Problem& p = hs->p;
+    p.t = t_rem;
+    p.tol_rate = tol_rate;
+    p.t_init = o.t_init;
+    p.shrink = o.shrink;
+    p.quad_rel_tol = o.quad_rel_tol;
+    p.m = k;
+    p.n_substeps = o.n_substeps;
+    p.quad_max_level = o.quad_max_level;
+    p.quad_min_level = o.quad_min_level;
+    p.max_halvings = o.max_halvings;
+    hs->k_limit = k;
+    hs->h = h;
+    hs->breakdown = breakdown ? 1 : 0;
+    hs->first = first ? 1 : 0;
+    hs->tau_prev = tau_prev;
+    for (int i = 0; i < k; ++i) {
+        hs->alpha[i] = alpha[i];
+        hs->beta[i] = (i < k - 1) ? beta[i] : 0.0;
+        hs->s[i] = 1.0;
+    }
+    DevState* d = (DevState*)dev_alloc(sizeof(DevState));
+    if (!d) {
+        delete hs;
+        return fail(TE_ERR_OUT_OF_MEMORY, "device allocation failed");
+    }
+    auto chk = [&](hipError_t e, const char* what) {
+        if (e != hipSuccess && rc == TE_OK) rc = fail(TE_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    };
+    chk(hipMemcpyAsync(d, hs, sizeof(DevState), hipMemcpyHostToDevice, s), "copy");
+    if (rc == TE_OK) chk(launch_step_only(d, s), "launch");
+    if (rc == TE_OK) chk(hipMemcpyAsync(hs, d, sizeof(DevState), hipMemcpyDeviceToHost, s), "copy");
+    if (rc == TE_OK) chk(hipStreamSynchronize(s), "sync");
+    dev_free(d);
+    if (rc == TE_OK) {
+        *tau = hs->last_tau;
+        *err = hs->last_err;
+        for (int i = 0; i < k; ++i) {
+            omega[i].re = hs->omega[i].x;
+            omega[i].im = hs->omega[i].y;
+        }
+        if (warnings) *warnings = (uint32_t)hs->warnings;
+        if (hs->status == TE_ERR_STEP_UNDERFLOW) rc = fail(TE_ERR_STEP_UNDERFLOW, "no admissible step");
+        else if (hs->status != TE_OK) rc = fail(hs->status, "device-side failure in the step search");
+    }
+    delete hs;
+    return rc;
+}
+
+}  // extern "C"

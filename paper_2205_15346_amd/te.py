@@ -1,0 +1,277 @@
+"""Thin Python binding of libtimeevolve (include/te.h): argument marshalling only.
+
+Every function carries the C name and forwards to the HIP library; device buffers are
+torch.complex128 / float64 tensors on the current HIP device, and the current torch stream is
+passed as the hipStream_t.  There is no fallback: if the library is missing this module
+raises at import time.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtimeevolve.so")
+
+TE_OK = 0
+TE_ERR_INVALID_ARG = 1
+TE_ERR_INVALID_CSR = 2
+TE_ERR_NOT_HERMITIAN = 3
+TE_ERR_UNSUPPORTED = 4
+TE_ERR_OUT_OF_MEMORY = 5
+TE_ERR_DEVICE = 6
+TE_ERR_STEP_UNDERFLOW = 7
+TE_ERR_NONFINITE = 8
+TE_ERR_CAPACITY = 9
+TE_WARN_NUMERICAL = 1
+TE_WARN_QUADRATURE = 2
+TE_PTR_DEVICE = 1
+TE_CHECK_HERMITIAN = 2
+TE_MAX_KRYLOV = 64
+
+
+class te_c128(ctypes.Structure):
+    _fields_ = [("re", ctypes.c_double), ("im", ctypes.c_double)]
+
+
+class te_options(ctypes.Structure):
+    _fields_ = [("n_substeps", ctypes.c_int32), ("t_init", ctypes.c_double), ("shrink", ctypes.c_double),
+                ("quad_rel_tol", ctypes.c_double), ("quad_max_level", ctypes.c_int32),
+                ("quad_min_level", ctypes.c_int32), ("max_halvings", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class te_result(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int32), ("matvecs", ctypes.c_int32), ("breakdown_dim", ctypes.c_int32),
+                ("warnings", ctypes.c_uint32), ("err_bound", ctypes.c_double),
+                ("num_err_estimate", ctypes.c_double), ("t_reached", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class TEError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{message} (status {status})")
+        self.status = status
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libtimeevolve.so is not built ({LIB_PATH}); run `python -m paper_2205_15346_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_P = ctypes.c_void_p
+_D = ctypes.c_double
+_I = ctypes.c_int32
+_I64 = ctypes.c_int64
+_PD = ctypes.POINTER(ctypes.c_double)
+_PI = ctypes.POINTER(ctypes.c_int32)
+_PU = ctypes.POINTER(ctypes.c_uint32)
+
+_SIGS = {
+    "te_default_options": (None, [ctypes.POINTER(te_options)]),
+    "te_status_string": (ctypes.c_char_p, [_I]),
+    "te_last_error": (ctypes.c_char_p, []),
+    "te_hamiltonian_create": (_I, [ctypes.POINTER(_P), _I64, _I64, _P, _P, _P, ctypes.c_uint32, _P]),
+    "te_hamiltonian_destroy": (_I, [_P]),
+    "te_hamiltonian_info": (_I, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), _PD]),
+    "te_workspace_bytes": (ctypes.c_size_t, [_I64, _I]),
+    "te_set_allocator": (_I, [_P, _P, _P]),
+    "te_evolve": (_I, [_P, _P, _P, _D, _D, _I, ctypes.POINTER(te_options), ctypes.POINTER(te_result), _P]),
+    "te_spmv": (_I, [_P, _P, _P, ctypes.POINTER(te_c128), _P]),
+    "te_arnoldi": (_I, [_P, _P, _I, _D, _P, _PD, _PD, _PI, _P]),
+    "te_tridiag_eig": (_I, [_I, _PD, _PD, _PD, _PD, _P]),
+    "te_error_integral": (_I, [_I, _PD, _PD, _D, _D, _D, ctypes.POINTER(te_options), _PD, _PI, _PI, _P]),
+    "te_step_search": (_I, [_I, _PD, _PD, _D, _D, _D, _I, _D, _I, ctypes.POINTER(te_options), _PD, _PD,
+                            ctypes.POINTER(te_c128), _PU, _P]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def _check(status):
+    if status != TE_OK:
+        raise TEError(status, _lib.te_last_error().decode() or _lib.te_status_string(status).decode())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_c128(t, name, dim=None):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous complex128 CUDA tensor")
+    if dim is not None and t.numel() != dim:
+        raise ValueError(f"{name} must have {dim} elements")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _f64(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_PD)
+
+
+def te_default_options(**overrides) -> te_options:
+    o = te_options()
+    _lib.te_default_options(ctypes.byref(o))
+    for k, v in overrides.items():
+        setattr(o, k, v)
+    return o
+
+
+def te_status_string(status: int) -> str:
+    return _lib.te_status_string(status).decode()
+
+
+def te_workspace_bytes(dim: int, m: int) -> int:
+    return int(_lib.te_workspace_bytes(dim, m))
+
+
+class Hamiltonian:
+    """Owner of a te_hamiltonian handle (te_hamiltonian_create / te_hamiltonian_destroy)."""
+
+    def __init__(self, handle):
+        self._h = handle
+        dim, nnz, n1 = _I64(), _I64(), _D()
+        _check(_lib.te_hamiltonian_info(self._h, ctypes.byref(dim), ctypes.byref(nnz), ctypes.byref(n1)))
+        self.dim, self.nnz, self.norm1 = dim.value, nnz.value, n1.value
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("Hamiltonian already destroyed")
+        return self._h
+
+    def destroy(self):
+        if self._h is not None:
+            _check(_lib.te_hamiltonian_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.destroy()
+
+
+def te_hamiltonian_create(row_ptr, col_idx, values, check_hermitian=False, stream=None) -> Hamiltonian:
+    """From host NumPy arrays (int32, int32, complex128) or CUDA tensors of the same dtypes."""
+    import torch
+    flags = TE_CHECK_HERMITIAN if check_hermitian else 0
+    keep = []
+    if isinstance(values, torch.Tensor):
+        flags |= TE_PTR_DEVICE
+        rp, ci, va = row_ptr.contiguous(), col_idx.contiguous(), values.contiguous()
+        if rp.dtype != torch.int32 or ci.dtype != torch.int32 or va.dtype != torch.complex128:
+            raise TypeError("device CSR needs int32, int32, complex128 tensors")
+        keep += [rp, ci, va]
+        ptrs = [ctypes.c_void_p(x.data_ptr()) for x in (rp, ci, va)]
+        dim, nnz = rp.numel() - 1, ci.numel()
+    else:
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+        va = np.ascontiguousarray(values, dtype=np.complex128)
+        keep += [rp, ci, va]
+        ptrs = [ctypes.c_void_p(x.ctypes.data) for x in (rp, ci, va)]
+        dim, nnz = rp.size - 1, ci.size
+    h = _P()
+    _check(_lib.te_hamiltonian_create(ctypes.byref(h), dim, nnz, *ptrs, flags, _stream(stream)))
+    return Hamiltonian(h)
+
+
+def te_evolve(H: Hamiltonian, v0, t: float, tol: float, m: int, options=None, out=None, stream=None):
+    """v(t) = exp(-iHt) v0; returns (v_out tensor, te_result)."""
+    import torch
+    p0 = _dev_c128(v0, "v0", H.dim)
+    if out is None:
+        out = torch.empty_like(v0)
+    p1 = _dev_c128(out, "out", H.dim)
+    res = te_result()
+    opt = ctypes.byref(options) if options is not None else None
+    _check(_lib.te_evolve(H.handle, p0, p1, float(t), float(tol), int(m), opt, ctypes.byref(res), _stream(stream)))
+    return out, res
+
+
+def te_spmv(H: Hamiltonian, x, y=None, stream=None):
+    """y = H x and x^H y; returns (y, complex)."""
+    import torch
+    px = _dev_c128(x, "x", H.dim)
+    if y is None:
+        y = torch.empty_like(x)
+    py = _dev_c128(y, "y", H.dim)
+    d = te_c128()
+    _check(_lib.te_spmv(H.handle, px, py, ctypes.byref(d), _stream(stream)))
+    return y, complex(d.re, d.im)
+
+
+def te_arnoldi(H: Hamiltonian, u, m: int, tol_rate: float, stream=None):
+    """Krylov basis of u: returns (V [k, dim] tensor view, alpha[k], beta[k], k)."""
+    import torch
+    pu = _dev_c128(u, "u", H.dim)
+    mm = min(m, H.dim)
+    V = torch.empty((mm, H.dim), dtype=torch.complex128, device=u.device)
+    alpha = np.zeros(mm)
+    beta = np.zeros(mm)
+    k = _I()
+    _check(_lib.te_arnoldi(H.handle, pu, int(m), float(tol_rate), ctypes.c_void_p(V.data_ptr()),
+                           alpha.ctypes.data_as(_PD), beta.ctypes.data_as(_PD), ctypes.byref(k), _stream(stream)))
+    kk = k.value
+    return V[:kk], alpha[:kk], beta[:kk], kk
+
+
+def te_tridiag_eig(alpha, beta, stream=None):
+    """Eigen-decomposition of the tridiagonal (alpha, beta): returns (lambda[k], Q[k, k])."""
+    a, pa = _f64(alpha)
+    k = a.size
+    b, pb = _f64(beta if k > 1 else np.zeros(1))
+    lam = np.zeros(k)
+    Q = np.zeros(k * k)
+    _check(_lib.te_tridiag_eig(k, pa, pb, lam.ctypes.data_as(_PD), Q.ctypes.data_as(_PD), _stream(stream)))
+    return lam, Q.reshape(k, k).T.copy()  # C layout is column-major
+
+
+def te_error_integral(lam, coef, h, a, b, options=None, stream=None):
+    """Device tanh-sinh integral of h |sum coef_n exp(-i lam_n tau)| over [a, b]: (value, level, converged)."""
+    l_, pl = _f64(lam)
+    c_, pc = _f64(coef)
+    val = _D()
+    lev = _I()
+    conv = _I()
+    opt = ctypes.byref(options) if options is not None else None
+    _check(_lib.te_error_integral(l_.size, pl, pc, float(h), float(a), float(b), opt, ctypes.byref(val),
+                                  ctypes.byref(lev), ctypes.byref(conv), _stream(stream)))
+    return val.value, lev.value, bool(conv.value)
+
+
+def te_step_search(alpha, beta, h, tol_rate, t_rem, first, tau_prev, breakdown, options=None, stream=None):
+    """Step-size search of one restart: returns (tau, err, omega[k] complex, warnings)."""
+    a, pa = _f64(alpha)
+    k = a.size
+    b, pb = _f64(beta if k > 1 else np.zeros(1))
+    tau, err = _D(), _D()
+    om = (te_c128 * k)()
+    warn = ctypes.c_uint32()
+    opt = ctypes.byref(options) if options is not None else None
+    _check(_lib.te_step_search(k, pa, pb, float(h), float(tol_rate), float(t_rem), int(bool(first)),
+                               float(tau_prev), int(bool(breakdown)), opt, ctypes.byref(tau), ctypes.byref(err),
+                               om, ctypes.byref(warn), _stream(stream)))
+    omega = np.array([complex(z.re, z.im) for z in om])
+    return tau.value, err.value, omega, warn.value
+
+
+def exported_symbols():
+    """Names of the C functions this binding wraps (all declared in include/te.h)."""
+    return sorted(_SIGS)
