@@ -75,7 +75,7 @@ typedef struct {
     int32_t quad_max_level; /* refinements before TE_WARN_QUADRATURE */
     int32_t quad_min_level; /* refinements always taken */
     int32_t max_halvings;   /* cap of the halving loop (TE_ERR_STEP_UNDERFLOW) */
-    uint32_t flags;         /* reserved, must be 0 */
+    uint32_t flags;         /* TE_OPT_* bits (below); other bits must be 0 */
 } te_options;
 
 typedef struct {
@@ -87,6 +87,29 @@ typedef struct {
     double num_err_estimate; /* ||v0|| * accumulated d*||H||_1*2^-52 (eq. numericalError) */
     double t_reached;        /* == t on success */
 } te_result;
+
+/* te_options.flags bit: time every kernel of te_evolve with HIP events on the caller's
+ * stream (restarts are then launched directly instead of as a graph) and record the
+ * per-kernel durations and algorithmic bytes, read back with te_last_profile(). */
+#define TE_OPT_PROFILE 1u
+
+/* Kernel classes of one restart, in te_profile order. */
+enum {
+    TE_KERNEL_PROJECT = 0, /* sparse product fused with all projections and the Gram column */
+    TE_KERNEL_UPDATE = 1,  /* new basis vector and its norm */
+    TE_KERNEL_STEP = 2,    /* eigensolve, error integrals, step search, restart control */
+    TE_KERNEL_COMBINE = 3, /* recombination w = V omega */
+    TE_KERNEL_CLASSES = 4
+};
+
+/* Per-kernel-class totals of the last profiled te_evolve on a handle.  bytes are the
+ * algorithmic bytes of each launch (one read of every operand and one write of every
+ * result it must touch); launches after a lucky breakdown that do no work are excluded. */
+typedef struct {
+    int64_t launches[TE_KERNEL_CLASSES];
+    double seconds[TE_KERNEL_CLASSES];
+    double bytes[TE_KERNEL_CLASSES];
+} te_profile;
 
 void te_default_options(te_options* opt);
 const char* te_status_string(te_status s);
@@ -134,6 +157,9 @@ te_status te_set_allocator(te_alloc_fn alloc, te_free_fn free_fn, void* ctx);
  * Calls on one handle are serialised (the handle holds one workspace). */
 te_status te_evolve(te_hamiltonian h, const te_c128* v0, te_c128* v_out, double t, double tol,
                     int32_t m, const te_options* opt, te_result* res, void* stream);
+
+/* Totals recorded by the last te_evolve on h that ran with TE_OPT_PROFILE (zeros if none). */
+te_status te_last_profile(te_hamiltonian h, te_profile* out);
 
 /* ---------------------------------------------------------------------------------------
  * Component entry points: each runs one step of the hot path with the same kernels that

@@ -228,8 +228,11 @@ def krylov_coefficients(lam: np.ndarray, U: np.ndarray, tau: float) -> np.ndarra
 
 
 def evolve(H, v0: np.ndarray, t: float, tol: float, m: int, opts: Optional[Options] = None,
-           norm1: Optional[float] = None) -> EvolveResult:
-    """Alg. 1: approximate exp(-iHt) v0 with the a-posteriori bound of eq. errorIntegral."""
+           norm1: Optional[float] = None, max_steps: Optional[int] = None) -> EvolveResult:
+    """Alg. 1: approximate exp(-iHt) v0 with the a-posteriori bound of eq. errorIntegral.
+
+    ``max_steps`` (harness use only, e.g. timing a bounded sample) stops after that many
+    restarts and returns the state reached at t_reached < t."""
     opts = opts or Options()
     if not (np.isfinite(t) and t >= 0.0) or not (np.isfinite(tol) and tol > 0.0) or m < 2:
         raise ValueError("need t >= 0 finite, tol > 0 finite, m >= 2")
@@ -277,5 +280,7 @@ def evolve(H, v0: np.ndarray, t: float, tol: float, m: int, opts: Optional[Optio
         if ar.breakdown:
             breakdown_dim = ar.k
             t_now = t
+        if max_steps is not None and steps >= max_steps:
+            break
     return EvolveResult(beta0 * w, steps, matvecs, beta0 * err_acc, beta0 * num_acc, warnings,
                         breakdown_dim, t_now, trace)

@@ -1,21 +1,30 @@
 """MI355X-native restarted Krylov evolution exp(-iHt) v with a rigorous a-posteriori bound.
 
 The computation lives in libtimeevolve.so (HIP for gfx950, C ABI in include/te.h); this
-package only loads it (`te`), builds it (`build`) and offers convenience wrappers.
+package only builds it (`build`), loads it (`te`, on first use: importing the package does
+not touch the library, so it can be rebuilt in place) and offers convenience wrappers.
+Using any of the names below without a built library raises ImportError.
 """
 
-from . import te
-from .te import (Hamiltonian, TEError, te_arnoldi, te_default_options, te_error_integral, te_evolve,
-                 te_hamiltonian_create, te_spmv, te_step_search, te_tridiag_eig, te_workspace_bytes)
+import importlib
+
+_TE_NAMES = ("Hamiltonian", "TEError", "te_arnoldi", "te_default_options", "te_error_integral", "te_evolve",
+             "te_hamiltonian_create", "te_last_profile", "te_spmv", "te_step_search", "te_tridiag_eig",
+             "te_workspace_bytes")
 
 
-def hamiltonian_from_csr(csr, check_hermitian=False, stream=None) -> Hamiltonian:
+def __getattr__(name):
+    if name == "te":
+        return importlib.import_module(".te", __name__)
+    if name in _TE_NAMES:
+        return getattr(importlib.import_module(".te", __name__), name)
+    raise AttributeError(name)
+
+
+def hamiltonian_from_csr(csr, check_hermitian=False, stream=None):
     """te_hamiltonian_create from any object with row_ptr / col / val host arrays."""
-    return te_hamiltonian_create(csr.row_ptr, csr.col, csr.val, check_hermitian=check_hermitian, stream=stream)
+    te = importlib.import_module(".te", __name__)
+    return te.te_hamiltonian_create(csr.row_ptr, csr.col, csr.val, check_hermitian=check_hermitian, stream=stream)
 
 
-__all__ = [
-    "te", "Hamiltonian", "TEError", "te_arnoldi", "te_default_options", "te_error_integral", "te_evolve",
-    "te_hamiltonian_create", "te_spmv", "te_step_search", "te_tridiag_eig", "te_workspace_bytes",
-    "hamiltonian_from_csr",
-]
+__all__ = list(_TE_NAMES) + ["te", "hamiltonian_from_csr"]

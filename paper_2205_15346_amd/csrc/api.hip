@@ -78,6 +78,7 @@ struct Workspace {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t ev[2] = {nullptr, nullptr};
+    std::vector<hipEvent_t> pev[2];  // per-kernel timing events (profiling mode)
     size_t bytes = 0;
 
     static size_t layout(int dim, int m, const Tiling& tl, size_t* off_y, size_t* off_part, size_t* off_gpart,
@@ -107,6 +108,8 @@ struct Workspace {
         if (graph) (void)hipGraphDestroy(graph);
         for (auto& e : ev)
             if (e) (void)hipEventDestroy(e);
+        for (auto& v : pev)
+            for (auto& e : v) (void)hipEventDestroy(e);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         if (host_flag) (void)hipHostFree(host_flag);
         dev_free(base);
@@ -123,6 +126,7 @@ struct te_hamiltonian_s {
     double norm1 = 0.0;
     std::mutex mu;
     Workspace* ws = nullptr;
+    te_profile prof{};
     ~te_hamiltonian_s() {
         delete ws;
         dev_free(row_ptr);
@@ -188,6 +192,58 @@ hipError_t enqueue_restart(te_hamiltonian h, Workspace* w, hipStream_t s) {
     return e;
 }
 
+// restart with an event before the first and after every kernel (profiling mode)
+hipError_t enqueue_restart_profiled(te_hamiltonian h, Workspace* w, hipStream_t s, std::vector<hipEvent_t>& E) {
+    hipError_t e = hipEventRecord(E[0], s);
+    for (int j = 0; j < w->m && e == hipSuccess; ++j) {
+        e = launch_project(w->tl, h->csr, w->V, w->ld, j, w->y, w->st, w->rb, s);
+        if (e == hipSuccess) e = hipEventRecord(E[2 * j + 1], s);
+        if (e == hipSuccess) e = launch_update(w->tl, w->V, w->ld, w->dim, j, w->y, w->st, w->rb, s);
+        if (e == hipSuccess) e = hipEventRecord(E[2 * j + 2], s);
+    }
+    if (e == hipSuccess) e = launch_step(w->st, w->host_flag_dev, s);
+    if (e == hipSuccess) e = hipEventRecord(E[2 * w->m + 1], s);
+    if (e == hipSuccess) e = launch_combine(w->tl, w->V, w->ld, w->dim, w->st, s);
+    if (e == hipSuccess) e = hipEventRecord(E[2 * w->m + 2], s);
+    return e;
+}
+
+// add one finished restart with Krylov dimension k to the profile
+hipError_t accumulate_profile(te_hamiltonian h, Workspace* w, std::vector<hipEvent_t>& E, int k, te_profile* p) {
+    const double d = (double)w->dim, nnz = (double)h->csr.nnz;
+    auto span = [&](int a, int b, double* out) {
+        float ms = 0.f;
+        hipError_t e = hipEventElapsedTime(&ms, E[a], E[b]);
+        *out = 1e-3 * (double)ms;
+        return e;
+    };
+    double t;
+    for (int j = 0; j < k; ++j) {
+        hipError_t e = span(2 * j, 2 * j + 1, &t);
+        if (e != hipSuccess) return e;
+        p->launches[TE_KERNEL_PROJECT] += 1;
+        p->seconds[TE_KERNEL_PROJECT] += t;
+        // CSR (values, columns, row pointers), columns 0..j of V, y written
+        p->bytes[TE_KERNEL_PROJECT] += 20.0 * nnz + 4.0 * (d + 1) + 16.0 * d * (j + 2);
+        e = span(2 * j + 1, 2 * j + 2, &t);
+        if (e != hipSuccess) return e;
+        p->launches[TE_KERNEL_UPDATE] += 1;
+        p->seconds[TE_KERNEL_UPDATE] += t;
+        // y and columns 0..j read, column j+1 written unless this is the last iteration
+        p->bytes[TE_KERNEL_UPDATE] += 16.0 * d * (j + 2) + ((j + 1 < w->m) ? 16.0 * d : 0.0);
+    }
+    hipError_t e = span(2 * w->m, 2 * w->m + 1, &t);
+    if (e != hipSuccess) return e;
+    p->launches[TE_KERNEL_STEP] += 1;
+    p->seconds[TE_KERNEL_STEP] += t;
+    e = span(2 * w->m + 1, 2 * w->m + 2, &t);
+    if (e != hipSuccess) return e;
+    p->launches[TE_KERNEL_COMBINE] += 1;
+    p->seconds[TE_KERNEL_COMBINE] += t;
+    p->bytes[TE_KERNEL_COMBINE] += 16.0 * d * (k + 1);
+    return hipSuccess;
+}
+
 bool graphs_enabled() {
     const char* v = std::getenv("TE_NO_GRAPH");
     return !(v && v[0] == '1');
@@ -246,7 +302,7 @@ Problem make_problem(te_hamiltonian h, const te_options& o, double t, double tol
 te_status check_options(const te_options& o) {
     if (o.n_substeps < 1 || !(o.t_init > 0.0) || !std::isfinite(o.t_init) || !(o.shrink > 0.0) || !(o.shrink <= 1.0) ||
         !(o.quad_rel_tol > 0.0) || o.quad_max_level < 0 || o.quad_max_level > 20 || o.quad_min_level < 0 ||
-        o.max_halvings < 0 || o.flags != 0)
+        o.max_halvings < 0 || (o.flags & ~TE_OPT_PROFILE) != 0)
         return fail(TE_ERR_INVALID_ARG, "invalid te_options");
     return TE_OK;
 }
@@ -401,19 +457,37 @@ te_status te_evolve(te_hamiltonian h, const te_c128* v0, te_c128* v_out, double 
     rc = get_workspace(h, mm, &w);
     if (rc != TE_OK) return rc;
     const Problem prob = make_problem(h, o, t, tol, mm);
-    *(volatile int*)w->host_flag = 0;
+    volatile int* flag = (volatile int*)w->host_flag;
+    for (int i = 0; i < 16; ++i) flag[i] = 0;
+    const bool profile = (o.flags & TE_OPT_PROFILE) != 0;
+    if (profile) {
+        h->prof = te_profile{};
+        for (auto& v : w->pev) {
+            while ((int)v.size() < 2 * mm + 3) {
+                hipEvent_t e;
+                TE_HIP(hipEventCreate(&e));
+                v.push_back(e);
+            }
+        }
+    }
     TE_HIP(launch_init(w->tl, (const double2*)v0, w->V, dim, w->st, w->rb, prob, s));
     const long max_restarts = 100000000L;
     long r = 0;
     for (;; ++r) {
-        if (w->exec) TE_HIP(hipGraphLaunch(w->exec, s));
+        if (profile) TE_HIP(enqueue_restart_profiled(h, w, s, w->pev[r & 1]));
+        else if (w->exec) TE_HIP(hipGraphLaunch(w->exec, s));
         else TE_HIP(enqueue_restart(h, w, s));
         TE_HIP(hipEventRecord(w->ev[r & 1], s));
         if (r >= 1) {
             TE_HIP(hipEventSynchronize(w->ev[(r - 1) & 1]));
-            if (*(volatile int*)w->host_flag) break;
+            if (profile && r - 1 < flag[1]) TE_HIP(accumulate_profile(h, w, w->pev[(r - 1) & 1], flag[8 + ((r - 1) & 7)], &h->prof));
+            if (flag[0]) break;
         }
         if (r >= max_restarts) return fail(TE_ERR_DEVICE, "restart limit reached");
+    }
+    if (profile) {
+        TE_HIP(hipEventSynchronize(w->ev[r & 1]));
+        if (r < flag[1]) TE_HIP(accumulate_profile(h, w, w->pev[r & 1], flag[8 + (r & 7)], &h->prof));
     }
     TE_HIP(launch_output(w->tl, w->V, (double2*)v_out, dim, w->st, s));
     DevState hs;
@@ -435,6 +509,13 @@ te_status te_evolve(te_hamiltonian h, const te_c128* v0, te_c128* v_out, double 
         return fail(hs.status, "device-side failure (eigensolver did not converge)");
     }
     if (hs.beta0 == 0.0 && res) res->t_reached = t;
+    return TE_OK;
+}
+
+te_status te_last_profile(te_hamiltonian h, te_profile* out) {
+    if (!h || !out) return fail(TE_ERR_INVALID_ARG, "null pointer");
+    std::lock_guard<std::mutex> lock(h->mu);
+    *out = h->prof;
     return TE_OK;
 }
 

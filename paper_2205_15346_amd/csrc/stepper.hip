@@ -416,7 +416,13 @@ __device__ void step_body(DevState* st, int* host_flag, bool controller) {
         if (tn >= P.t) st->done = 1;
         st->k_limit = P.m;
         st->breakdown = 0;
-        if (host_flag) __hip_atomic_store(host_flag, st->done, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        if (host_flag) {
+            // host_flag[0] done, [1] restarts completed, [8 + r % 8] Krylov dimension of restart r
+            const int r = st->steps - 1;
+            __hip_atomic_store(host_flag + 8 + (r & 7), k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(host_flag + 1, st->steps, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(host_flag, st->done, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
     }
 }
 

@@ -49,6 +49,18 @@ class te_result(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+TE_OPT_PROFILE = 1
+KERNEL_CLASSES = ("project", "update", "step", "combine")
+
+
+class te_profile(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64 * 4), ("seconds", ctypes.c_double * 4), ("bytes", ctypes.c_double * 4)]
+
+    def as_dict(self):
+        return {name: {"launches": int(self.launches[i]), "seconds": float(self.seconds[i]),
+                       "bytes": float(self.bytes[i])} for i, name in enumerate(KERNEL_CLASSES)}
+
+
 class TEError(RuntimeError):
     def __init__(self, status, message):
         super().__init__(f"{message} (status {status})")
@@ -77,6 +89,7 @@ _SIGS = {
     "te_workspace_bytes": (ctypes.c_size_t, [_I64, _I]),
     "te_set_allocator": (_I, [_P, _P, _P]),
     "te_evolve": (_I, [_P, _P, _P, _D, _D, _I, ctypes.POINTER(te_options), ctypes.POINTER(te_result), _P]),
+    "te_last_profile": (_I, [_P, ctypes.POINTER(te_profile)]),
     "te_spmv": (_I, [_P, _P, _P, ctypes.POINTER(te_c128), _P]),
     "te_arnoldi": (_I, [_P, _P, _I, _D, _P, _PD, _PD, _PI, _P]),
     "te_tridiag_eig": (_I, [_I, _PD, _PD, _PD, _PD, _P]),
@@ -203,6 +216,12 @@ def te_evolve(H: Hamiltonian, v0, t: float, tol: float, m: int, options=None, ou
     opt = ctypes.byref(options) if options is not None else None
     _check(_lib.te_evolve(H.handle, p0, p1, float(t), float(tol), int(m), opt, ctypes.byref(res), _stream(stream)))
     return out, res
+
+
+def te_last_profile(H: Hamiltonian) -> te_profile:
+    p = te_profile()
+    _check(_lib.te_last_profile(H.handle, ctypes.byref(p)))
+    return p
 
 
 def te_spmv(H: Hamiltonian, x, y=None, stream=None):

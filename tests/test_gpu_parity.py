@@ -4,7 +4,10 @@ to end, plus the ABI's error paths.  Tolerances:
   alpha / beta            1e-11 relative to ||H||_1 (different orthogonalisation order)
   basis orthogonality     1e-12
   eigen-decomposition     residual 50 k eps ||J||, orthogonality 50 k eps
-  quadrature              1e-12 relative to the oracle on identical inputs (same nodes)
+  quadrature              1e-12 relative to the oracle on identical inputs (same nodes), or
+                          2 h k eps (b - a): f = h|sum_n c_n exp(-i lam_n tau)| is known only to
+                          within its rounding floor h k eps, so integrals at that floor differ
+                          between any two FP64 evaluations
   evolution               ||v_gpu - v_oracle|| <= 2 tol + 1e-12 and each within its bound
                           of the exact answer where one is available."""
 
@@ -131,7 +134,8 @@ def _spectrum(k, seed):
     return a, b, lam, U
 
 
-@pytest.mark.parametrize("k,a,bnd", [(2, 0.0, 1.0), (6, 0.0, 0.3), (12, 0.5, 2.5), (40, 0.0, 4.0), (40, 1.0, 1.1)])
+@pytest.mark.parametrize("k,a,bnd", [(2, 0.0, 1.0), (6, 0.0, 0.3), (12, 0.5, 2.5), (40, 0.0, 4.0), (40, 1.0, 1.1),
+                                     (40, 5.0, 30.0), (64, 0.0, 50.0), (20, 0.0, 12.0)])
 def test_error_integral_matches_oracle(k, a, bnd):
     announce(f"integral k={k} [{a},{bnd}]")
     al, be, lam, U = _spectrum(k, k)
@@ -141,9 +145,12 @@ def test_error_integral_matches_oracle(k, a, bnd):
     lam_j, Q = np.linalg.eigh(J)
     val, level, conv = lib().te_error_integral(lam_j, Q[k - 1, :] * Q[0, :], h, a, bnd)
     f = O.bound_integrand(lam, U, h)
-    ref = O.tanh_sinh(f, a, bnd, abs_tol=h * k * 2.0 ** -52 * (bnd - a))
-    assert conv == ref.converged and level == ref.level
-    assert abs(val - ref.value) <= 1e-12 * abs(ref.value) + 1e-300
+    floor = h * k * 2.0 ** -52 * (bnd - a)
+    ref = O.tanh_sinh(f, a, bnd, abs_tol=floor)
+    assert conv == ref.converged
+    assert abs(val - ref.value) <= 1e-12 * abs(ref.value) + 2 * floor
+    if ref.value > 1e3 * floor:  # well above the floor both sides take the same number of levels
+        assert level == ref.level
 
 
 @pytest.mark.parametrize("k,first,breakdown,tau_prev,t_rem", [
@@ -158,7 +165,7 @@ def test_step_search_matches_oracle(k, first, breakdown, tau_prev, t_rem):
     f = O.bound_integrand(lam, U, h)
     tau_o, err_o, ok = O.step_size(f, rate, t_rem, first, tau_prev, breakdown, noise_rate=h * k * 2.0 ** -52)
     assert tau == pytest.approx(tau_o, rel=1e-12)
-    assert err == pytest.approx(err_o, rel=1e-9, abs=1e-300)
+    assert abs(err - err_o) <= 1e-9 * abs(err_o) + 2 * h * k * 2.0 ** -52 * tau
     assert err <= rate * tau * (1 + 1e-12)
     # omega in the Lanczos basis = D^H (omega of Alg. 1 in the A = -iH basis), D = diag((-i)^j)
     om_o = O.krylov_coefficients(lam, U, tau) * (-1j) ** np.arange(k)
