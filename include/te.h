@@ -99,7 +99,8 @@ enum {
     TE_KERNEL_UPDATE = 1,  /* new basis vector and its norm */
     TE_KERNEL_STEP = 2,    /* eigensolve, error integrals, step search, restart control */
     TE_KERNEL_COMBINE = 3, /* recombination w = V omega */
-    TE_KERNEL_CLASSES = 4
+    TE_KERNEL_FOLD = 4,    /* fold of the projection partials + Gram correction (small) */
+    TE_KERNEL_CLASSES = 5
 };
 
 /* Per-kernel-class totals of the last profiled te_evolve on a handle.  bytes are the

@@ -81,8 +81,8 @@ struct Workspace {
     std::vector<hipEvent_t> pev[2];  // per-kernel timing events (profiling mode)
     size_t bytes = 0;
 
-    static size_t layout(int dim, int m, const Tiling& tl, size_t* off_y, size_t* off_part, size_t* off_gpart,
-                         size_t* off_cnt, size_t* off_st) {
+    static size_t layout(int dim, int m, const Tiling& tl, size_t* off_y, size_t* off_part, size_t* off_npart,
+                         size_t* off_red, size_t* off_st) {
         const size_t ld = align_up((size_t)dim, 64);
         size_t o = 0;
         o += (size_t)m * ld * sizeof(double2);
@@ -92,11 +92,11 @@ struct Workspace {
         *off_part = o;
         o += (size_t)kMaxVals * tl.n_tiles * sizeof(double2);
         o = align_up(o, 256);
-        *off_gpart = o;
-        o += (size_t)kMaxVals * tl.n_groups * sizeof(double2);
+        *off_npart = o;
+        o += (size_t)tl.n_tiles * sizeof(double);
         o = align_up(o, 256);
-        *off_cnt = o;
-        o += (size_t)(tl.n_groups + 1) * sizeof(unsigned);
+        *off_red = o;  // folded values, then the fold ticket
+        o += (size_t)kMaxVals * sizeof(double2) + 256;
         o = align_up(o, 256);
         *off_st = o;
         o += sizeof(DevState);
@@ -144,8 +144,8 @@ te_status make_workspace(te_hamiltonian h, int m, Workspace** out) {
     w->m = m;
     w->ld = (int64_t)align_up((size_t)w->dim, 64);
     w->tl = choose_tiling(w->dim);
-    size_t oy, op, og, oc, os;
-    w->bytes = Workspace::layout(w->dim, m, w->tl, &oy, &op, &og, &oc, &os);
+    size_t oy, op, on, orr, os;
+    w->bytes = Workspace::layout(w->dim, m, w->tl, &oy, &op, &on, &orr, &os);
     w->base = (char*)dev_alloc(w->bytes);
     if (!w->base) {
         delete w;
@@ -154,17 +154,16 @@ te_status make_workspace(te_hamiltonian h, int m, Workspace** out) {
     w->V = (double2*)w->base;
     w->y = (double2*)(w->base + oy);
     w->rb.part = (double2*)(w->base + op);
-    w->rb.gpart = (double2*)(w->base + og);
-    w->rb.gcnt = (unsigned*)(w->base + oc);
-    w->rb.fcnt = w->rb.gcnt + w->tl.n_groups;
+    w->rb.npart = (double*)(w->base + on);
+    w->rb.red = (double2*)(w->base + orr);
+    w->rb.cnt = (unsigned*)(w->base + orr + (size_t)kMaxVals * sizeof(double2));
     w->rb.n_tiles = w->tl.n_tiles;
-    w->rb.n_groups = w->tl.n_groups;
     w->st = (DevState*)(w->base + os);
     te_status rc = TE_OK;
     auto chk = [&](hipError_t e, const char* what) {
         if (e != hipSuccess && rc == TE_OK) rc = fail(TE_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
     };
-    chk(hipMemset(w->base + oc, 0, (size_t)(w->tl.n_groups + 1) * sizeof(unsigned)), "hipMemset");
+    chk(hipMemset(w->rb.cnt, 0, 256), "hipMemset");
     chk(hipMemset(w->st, 0, sizeof(DevState)), "hipMemset");
     chk(hipHostMalloc((void**)&w->host_flag, 64, hipHostMallocMapped | hipHostMallocCoherent), "hipHostMalloc");
     if (rc == TE_OK) chk(hipHostGetDevicePointer((void**)&w->host_flag_dev, w->host_flag, 0), "hipHostGetDevicePointer");
@@ -185,30 +184,38 @@ hipError_t enqueue_restart(te_hamiltonian h, Workspace* w, hipStream_t s) {
     hipError_t e = hipSuccess;
     for (int j = 0; j < w->m && e == hipSuccess; ++j) {
         e = launch_project(w->tl, h->csr, w->V, w->ld, j, w->y, w->st, w->rb, s);
+        if (e == hipSuccess) e = launch_reduce(j, w->st, w->rb, s);
         if (e == hipSuccess) e = launch_update(w->tl, w->V, w->ld, w->dim, j, w->y, w->st, w->rb, s);
     }
-    if (e == hipSuccess) e = launch_step(w->st, w->host_flag_dev, s);
+    if (e == hipSuccess) e = launch_step(w->st, w->rb, w->host_flag_dev, s);
     if (e == hipSuccess) e = launch_combine(w->tl, w->V, w->ld, w->dim, w->st, s);
     return e;
 }
 
 // restart with an event before the first and after every kernel (profiling mode)
+// restart with an event before the first and after every kernel (profiling mode);
+// iteration j: E[3j] project E[3j+1] fold E[3j+2] update E[3j+3]; then step, combine
 hipError_t enqueue_restart_profiled(te_hamiltonian h, Workspace* w, hipStream_t s, std::vector<hipEvent_t>& E) {
     hipError_t e = hipEventRecord(E[0], s);
     for (int j = 0; j < w->m && e == hipSuccess; ++j) {
         e = launch_project(w->tl, h->csr, w->V, w->ld, j, w->y, w->st, w->rb, s);
-        if (e == hipSuccess) e = hipEventRecord(E[2 * j + 1], s);
+        if (e == hipSuccess) e = hipEventRecord(E[3 * j + 1], s);
+        if (e == hipSuccess) e = launch_reduce(j, w->st, w->rb, s);
+        if (e == hipSuccess) e = hipEventRecord(E[3 * j + 2], s);
         if (e == hipSuccess) e = launch_update(w->tl, w->V, w->ld, w->dim, j, w->y, w->st, w->rb, s);
-        if (e == hipSuccess) e = hipEventRecord(E[2 * j + 2], s);
+        if (e == hipSuccess) e = hipEventRecord(E[3 * j + 3], s);
     }
-    if (e == hipSuccess) e = launch_step(w->st, w->host_flag_dev, s);
-    if (e == hipSuccess) e = hipEventRecord(E[2 * w->m + 1], s);
+    if (e == hipSuccess) e = launch_step(w->st, w->rb, w->host_flag_dev, s);
+    if (e == hipSuccess) e = hipEventRecord(E[3 * w->m + 1], s);
     if (e == hipSuccess) e = launch_combine(w->tl, w->V, w->ld, w->dim, w->st, s);
-    if (e == hipSuccess) e = hipEventRecord(E[2 * w->m + 2], s);
+    if (e == hipSuccess) e = hipEventRecord(E[3 * w->m + 2], s);
     return e;
 }
 
-// add one finished restart with Krylov dimension k to the profile
+size_t profile_events(int m) { return (size_t)(3 * m + 3); }
+
+// add one finished restart with Krylov dimension k to the profile.  A build that broke down
+// at k < m still ran the projection of iteration k (its fold detected the breakdown).
 hipError_t accumulate_profile(te_hamiltonian h, Workspace* w, std::vector<hipEvent_t>& E, int k, te_profile* p) {
     const double d = (double)w->dim, nnz = (double)h->csr.nnz;
     auto span = [&](int a, int b, double* out) {
@@ -218,25 +225,31 @@ hipError_t accumulate_profile(te_hamiltonian h, Workspace* w, std::vector<hipEve
         return e;
     };
     double t;
-    for (int j = 0; j < k; ++j) {
-        hipError_t e = span(2 * j, 2 * j + 1, &t);
+    const int jp = std::min(k + 1, w->m);  // projections that ran
+    for (int j = 0; j < jp; ++j) {
+        hipError_t e = span(3 * j, 3 * j + 1, &t);
         if (e != hipSuccess) return e;
         p->launches[TE_KERNEL_PROJECT] += 1;
         p->seconds[TE_KERNEL_PROJECT] += t;
         // CSR (values, columns, row pointers), columns 0..j of V, y written
         p->bytes[TE_KERNEL_PROJECT] += 20.0 * nnz + 4.0 * (d + 1) + 16.0 * d * (j + 2);
-        e = span(2 * j + 1, 2 * j + 2, &t);
+        e = span(3 * j + 1, 3 * j + 2, &t);
+        if (e != hipSuccess) return e;
+        p->launches[TE_KERNEL_FOLD] += 1;
+        p->seconds[TE_KERNEL_FOLD] += t;
+        if (j >= k) continue;
+        e = span(3 * j + 2, 3 * j + 3, &t);
         if (e != hipSuccess) return e;
         p->launches[TE_KERNEL_UPDATE] += 1;
         p->seconds[TE_KERNEL_UPDATE] += t;
         // y and columns 0..j read, column j+1 written unless this is the last iteration
         p->bytes[TE_KERNEL_UPDATE] += 16.0 * d * (j + 2) + ((j + 1 < w->m) ? 16.0 * d : 0.0);
     }
-    hipError_t e = span(2 * w->m, 2 * w->m + 1, &t);
+    hipError_t e = span(3 * w->m, 3 * w->m + 1, &t);
     if (e != hipSuccess) return e;
     p->launches[TE_KERNEL_STEP] += 1;
     p->seconds[TE_KERNEL_STEP] += t;
-    e = span(2 * w->m + 1, 2 * w->m + 2, &t);
+    e = span(3 * w->m + 1, 3 * w->m + 2, &t);
     if (e != hipSuccess) return e;
     p->launches[TE_KERNEL_COMBINE] += 1;
     p->seconds[TE_KERNEL_COMBINE] += t;
@@ -463,14 +476,15 @@ te_status te_evolve(te_hamiltonian h, const te_c128* v0, te_c128* v_out, double 
     if (profile) {
         h->prof = te_profile{};
         for (auto& v : w->pev) {
-            while ((int)v.size() < 2 * mm + 3) {
+            while (v.size() < profile_events(mm)) {
                 hipEvent_t e;
                 TE_HIP(hipEventCreate(&e));
                 v.push_back(e);
             }
         }
     }
-    TE_HIP(launch_init(w->tl, (const double2*)v0, w->V, dim, w->st, w->rb, prob, s));
+    TE_HIP(launch_setup(w->st, prob, s));
+    TE_HIP(launch_copy((const double2*)v0, w->V, dim, s));
     const long max_restarts = 100000000L;
     long r = 0;
     for (;; ++r) {
@@ -489,7 +503,7 @@ te_status te_evolve(te_hamiltonian h, const te_c128* v0, te_c128* v_out, double 
         TE_HIP(hipEventSynchronize(w->ev[r & 1]));
         if (r < flag[1]) TE_HIP(accumulate_profile(h, w, w->pev[r & 1], flag[8 + (r & 7)], &h->prof));
     }
-    TE_HIP(launch_output(w->tl, w->V, (double2*)v_out, dim, w->st, s));
+    TE_HIP(launch_output(w->V, (double2*)v_out, dim, w->st, s));
     DevState hs;
     TE_HIP(hipMemcpyAsync(&hs, w->st, offsetof(DevState, alpha), hipMemcpyDeviceToHost, s));
     TE_HIP(hipStreamSynchronize(s));
@@ -541,11 +555,6 @@ te_status te_spmv(te_hamiltonian h, const te_c128* x, te_c128* y, te_c128* xhy, 
 
 }  // extern "C"
 
-namespace te {
-hipError_t launch_scale_columns(const double2* src, double2* dst, int64_t ld, int dim, int k, const DevState* st,
-                                hipStream_t s);
-}
-
 extern "C" {
 
 te_status te_arnoldi(te_hamiltonian h, const te_c128* u, int32_t m, double tol_rate, te_c128* V, double* alpha,
@@ -564,11 +573,14 @@ te_status te_arnoldi(te_hamiltonian h, const te_c128* u, int32_t m, double tol_r
     te_default_options(&o);
     Problem prob = make_problem(h, o, 1.0, 1.0, mm);
     prob.tol_rate = tol_rate;
-    TE_HIP(launch_init(w->tl, (const double2*)u, w->V, dim, w->st, w->rb, prob, s));
+    TE_HIP(launch_setup(w->st, prob, s));
+    TE_HIP(launch_copy((const double2*)u, w->V, dim, s));
     for (int j = 0; j < mm; ++j) {
         TE_HIP(launch_project(w->tl, h->csr, w->V, w->ld, j, w->y, w->st, w->rb, s));
+        TE_HIP(launch_reduce(j, w->st, w->rb, s));
         TE_HIP(launch_update(w->tl, w->V, w->ld, dim, j, w->y, w->st, w->rb, s));
     }
+    TE_HIP(launch_last_norm(w->st, w->rb, s));
     DevState hs;
     TE_HIP(hipMemcpyAsync(&hs, w->st, offsetof(DevState, ceff), hipMemcpyDeviceToHost, s));
     TE_HIP(hipStreamSynchronize(s));

@@ -3,14 +3,20 @@
 // (Alg. 1 step 3, w = V omega).
 //
 // Orthogonalisation scheme (differs from the paper's modified Gram-Schmidt, same result in
-// exact arithmetic): iteration j makes two passes over the basis.
-//   pass A  y = H v_j fused with all projections c'_i = v_i^H y and the Gram column
-//           g_i = v_i^H v_j (i <= j), one read of V_j;
-//   pass B  v_{j+1} = y - sum_i c_i v_i with c = G^{-1} c' (G = V^H V, first-order
-//           corrections), plus ||v_{j+1}||^2, one read of V_j and one write.
-// Using the measured Gram matrix keeps the new vector orthogonal to O(eps ||H||/beta)
-// without a second classical Gram-Schmidt sweep.  Normalisation is deferred: column i is
-// stored unnormalised and s[i] = 1/||column|| is applied on use.
+// exact arithmetic).  Iteration j makes two passes over the stored basis:
+//   project  y = H V[:, j] fused with c'_i = V[:, i]^H y and g_i = V[:, i]^H V[:, j] for all
+//            i <= j (one read of columns 0..j, raw = unnormalised);
+//   fold     (small) reduces the tile partials; ||V[:, j]|| = sqrt(g_j) is the norm of the
+//            previous residual (beta_{j-1}, breakdown test, scale s_j); corrects the
+//            coefficients with the measured Gram matrix, c = c' - E_{:,j} c'_j - E_{:,j-1} c'_{j-1}
+//            (E = G - I; the other columns of E multiply O(eps) coefficients);
+//   update   V[:, j+1] = s_j y - sum_i c_i s_i V[:, i] (one read of columns 0..j, one write).
+// The Gram correction keeps the new vector orthogonal to O(eps ||H|| / beta) without a
+// second classical Gram-Schmidt sweep.  Normalisation is deferred: column i is stored
+// unnormalised and s[i] = 1/||column i|| is applied where it is used.
+//
+// Tile partials are written with plain stores and folded by a later kernel, so the streaming
+// kernels carry no device-scope fences or atomics.
 #include <algorithm>
 #include <type_traits>
 
@@ -20,101 +26,78 @@ namespace te {
 
 Tiling choose_tiling(int dim) {
     Tiling t;
-    // aim for >= ~512 tiles on large problems (two per CU), more rows per thread only
-    // when the tile count stays high
-    int rpt = 1;
-    while (rpt < 8 && (int64_t)dim >= (int64_t)kBlock * rpt * 2 * 512) rpt *= 2;
-    t.rpt = rpt;
+    // two rows per thread once that still leaves >= 1024 tiles (4 workgroups per CU);
+    // measured on MI355X: 1-2 rows per thread stream at ~6.5 TB/s, 8 rows per thread at ~3.9.
+    t.rpt = ((int64_t)dim >= (int64_t)kBlock * 2 * 1024) ? 2 : 1;
     t.g = 4;
-    t.rows = kBlock * rpt;
+    t.rows = kBlock * t.rpt;
     t.n_tiles = (dim + t.rows - 1) / t.rows;
-    t.n_groups = (t.n_tiles + kGroup - 1) / kGroup;
     return t;
 }
 
-// ------------------------------------------------------------------------ init
-// V[:,0] = v0, ||v0||^2 -> beta0, s[0] = 1/beta0; the finisher also sets up the state.
-template <int RPT>
-__global__ __launch_bounds__(kBlock) void k_init(const double2* __restrict__ v0, double2* __restrict__ V,
-                                                  int dim, DevState* __restrict__ st, RedBuf rb, Problem prob) {
-    __shared__ double lds[kWaves];
-    __shared__ double2 vals[1];
-    const int rows = kBlock * RPT;
-    const int r0 = blockIdx.x * rows;
-    double acc = 0.0;
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-        const int r = r0 + threadIdx.x + q * kBlock;
-        if (r < dim) {
-            const double2 v = v0[r];
-            V[r] = v;
-            acc = fma(v.x, v.x, acc);
-            acc = fma(v.y, v.y, acc);
-        }
-    }
-    {
-        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-        double s = wave_sum(acc);
-        if (lane == 0) lds[wave] = s;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double b = 0.0;
-            for (int w = 0; w < kWaves; ++w) b += lds[w];
-            vals[0] = make_double2(b, 0.0);
-        }
-        __syncthreads();
-    }
-    if (!grid_reduce(vals, 1, blockIdx.x, rb)) return;
-    if (threadIdx.x == 0) {
-        const double nrm2 = vals[0].x;
-        st->p = prob;
-        st->t_now = 0.0;
-        st->tau_prev = prob.t_init;
-        st->err_acc = 0.0;
-        st->num_acc = 0.0;
-        st->first = 1;
-        st->done = 0;
-        st->do_combine = 0;
-        st->status = TE_OK;
-        st->steps = 0;
-        st->matvecs = 0;
-        st->breakdown_dim = 0;
-        st->warnings = 0;
-        st->k_limit = prob.m;
-        st->breakdown = 0;
-        st->k_comb = 0;
-        st->h = 0.0;
-        const double beta0 = sqrt(nrm2);
-        st->beta0 = beta0;
-        if (!isfinite(nrm2)) {
-            st->status = TE_ERR_NONFINITE;
-            st->done = 1;
-        } else if (beta0 == 0.0) {
-            st->done = 1;
-        } else {
-            st->s[0] = 1.0 / beta0;
-        }
-    }
+// ------------------------------------------------------------------- setup / copy
+__global__ void k_setup(DevState* __restrict__ st, Problem prob) {
+    if (threadIdx.x != 0) return;
+    st->p = prob;
+    st->beta0 = 0.0;
+    st->t_now = 0.0;
+    st->tau_prev = prob.t_init;
+    st->err_acc = 0.0;
+    st->num_acc = 0.0;
+    st->first = 1;
+    st->done = 0;
+    st->do_combine = 0;
+    st->status = TE_OK;
+    st->steps = 0;
+    st->matvecs = 0;
+    st->breakdown_dim = 0;
+    st->warnings = 0;
+    st->k_limit = prob.m;
+    st->breakdown = 0;
+    st->k_comb = 0;
+    st->norm_init = 1;
+    st->h = 0.0;
+    st->ys = 1.0;
+    st->s[0] = 1.0;
 }
 
-// -------------------------------------------------------------- pass A: SpMV + projections
+__global__ __launch_bounds__(kBlock) void k_copy(const double2* __restrict__ src, double2* __restrict__ dst, int dim) {
+    for (int r = blockIdx.x * kBlock + threadIdx.x; r < dim; r += gridDim.x * kBlock) dst[r] = src[r];
+}
+
+// -------------------------------------------------------------- project: SpMV + projections
+// Cross-lane reduction of 32 doubles per lane (8 columns x {Re, Im} x {y, x}): five halving
+// exchanges leave value (lane >> 1) in lanes 2q and 2q+1 after a last pairwise exchange;
+// 32 shuffles instead of 192 for independent butterflies.
+__device__ __forceinline__ double halving_reduce32(double (&a)[32], int lane) {
+#pragma unroll
+    for (int h = 16, o = 32; h >= 1; h >>= 1, o >>= 1) {
+        const bool hi = (lane & o) != 0;
+#pragma unroll
+        for (int v = 0; v < h; ++v) {
+            const double send = hi ? a[v] : a[v + h];
+            const double keep = hi ? a[v + h] : a[v];
+            a[v] = keep + __shfl_xor(send, o);
+        }
+    }
+    return a[0] + __shfl_xor(a[0], 1);
+}
+
 template <int RPT, int G>
 __global__ __launch_bounds__(kBlock) void k_project(const int* __restrict__ rp, const int* __restrict__ ci,
-                                                     const double2* __restrict__ val, double2* __restrict__ V,
+                                                     const double2* __restrict__ val, const double2* __restrict__ V,
                                                      int64_t ld, int dim, int j, double2* __restrict__ y,
-                                                     DevState* __restrict__ st, RedBuf rb) {
+                                                     const DevState* __restrict__ st, RedBuf rb) {
     constexpr int R = kBlock * RPT;
     __shared__ double2 ytile[R];
     __shared__ double2 wpart[kWaves][kMaxVals];
-    __shared__ double2 vals[kMaxVals];
     if (st->done || j >= st->k_limit) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r0 = blockIdx.x * R;
     const int r1 = min(r0 + R, dim);
-    const double sj = st->s[j];
     const double2* __restrict__ x = V + (int64_t)j * ld;
 
-    // y = s_j * H * V[:, j]  (G lanes per row, coalesced CSR stream)
+    // y = H V[:, j] (raw), G lanes per row streaming the CSR
     {
         const int lg = tid % G, grp = tid / G;
         for (int r = r0 + grp; r < r1; r += kBlock / G) {
@@ -127,15 +110,13 @@ __global__ __launch_bounds__(kBlock) void k_project(const int* __restrict__ rp, 
                 acc.y += __shfl_xor(acc.y, o);
             }
             if (lg == 0) {
-                const double2 yy = cscale(acc, sj);
-                y[r] = yy;
-                ytile[r - r0] = yy;
+                y[r] = acc;
+                ytile[r - r0] = acc;
             }
         }
     }
     __syncthreads();
 
-    // projections of y and of x on every stored column i <= j
     double2 yq[RPT], xq[RPT];
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
@@ -148,25 +129,38 @@ __global__ __launch_bounds__(kBlock) void k_project(const int* __restrict__ rp, 
             xq[q] = make_double2(0.0, 0.0);
         }
     }
-    for (int i = 0; i <= j; ++i) {
-        const double2* __restrict__ vi = V + (int64_t)i * ld;
-        double2 cy = make_double2(0.0, 0.0), cx = make_double2(0.0, 0.0);
+    // projections on columns 0..j in batches of 8
+    for (int i0 = 0; i0 <= j; i0 += 8) {
+        double a[32];
 #pragma unroll
-        for (int q = 0; q < RPT; ++q) {
-            const int r = r0 + tid + q * kBlock;
-            if (r < r1) {
-                const double2 v = vi[r];
-                cy = cfma_conj(v, yq[q], cy);
-                cx = cfma_conj(v, xq[q], cx);
+        for (int b = 0; b < 8; ++b) {
+            double2 cy = make_double2(0.0, 0.0), cx = make_double2(0.0, 0.0);
+            const int i = i0 + b;
+            if (i <= j) {
+                const double2* __restrict__ vi = V + (int64_t)i * ld;
+#pragma unroll
+                for (int q = 0; q < RPT; ++q) {
+                    const int r = r0 + tid + q * kBlock;
+                    if (r < r1) {
+                        const double2 v = vi[r];
+                        cy = cfma_conj(v, yq[q], cy);
+                        cx = cfma_conj(v, xq[q], cx);
+                    }
+                }
             }
+            a[4 * b] = cy.x;
+            a[4 * b + 1] = cy.y;
+            a[4 * b + 2] = cx.x;
+            a[4 * b + 3] = cx.y;
         }
-        cy.x = wave_sum(cy.x);
-        cy.y = wave_sum(cy.y);
-        cx.x = wave_sum(cx.x);
-        cx.y = wave_sum(cx.y);
-        if (lane == 0) {
-            wpart[wave][2 * i] = cy;
-            wpart[wave][2 * i + 1] = cx;
+        const double s = halving_reduce32(a, lane);
+        if ((lane & 1) == 0) {
+            const int v = lane >> 1;  // 4 * column-in-batch + component
+            const int i = i0 + (v >> 2);
+            if (i <= j) {
+                double* dst = (double*)&wpart[wave][2 * i + ((v >> 1) & 1)];
+                dst[v & 1] = s;
+            }
         }
     }
     __syncthreads();
@@ -174,70 +168,129 @@ __global__ __launch_bounds__(kBlock) void k_project(const int* __restrict__ rp, 
     for (int v = tid; v < nv; v += kBlock) {
         double2 s = make_double2(0.0, 0.0);
         for (int w = 0; w < kWaves; ++w) s = cadd(s, wpart[w][v]);
-        vals[v] = s;
+        rb.part[(size_t)v * rb.n_tiles + blockIdx.x] = s;
     }
-    __syncthreads();
-    if (!grid_reduce(vals, nv, blockIdx.x, rb)) return;
+}
 
-    // finisher: scale, Gram column, corrected coefficients c = (I + E)^{-1} c'
-    __shared__ double2 cp[kMaxM + 1], c1[kMaxM + 1];
-    if (tid <= j) {
-        const double si = st->s[tid];
-        const double2 cy = cscale(vals[2 * tid], si);              // c'_i = v_i^H y
-        const double2 gx = cscale(vals[2 * tid + 1], si * sj);     // g_i  = v_i^H v_j
-        cp[tid] = cy;
-        st->G[tid * kMaxM + j] = gx;
-        st->G[j * kMaxM + tid] = make_double2(gx.x, -gx.y);
+// ---------------------------------------------------- fold of the projection partials
+// Block v folds value v over all tiles (fixed order); the last block to finish applies the
+// scales, the breakdown test and the Gram correction.
+__global__ __launch_bounds__(kBlock) void k_reduce(DevState* __restrict__ st, RedBuf rb, int j) {
+    __shared__ double lds[kWaves];
+    __shared__ double2 sv[kMaxVals];
+    __shared__ double2 cp[kMaxM + 1], g[kMaxM + 1];
+    __shared__ unsigned ticket;
+    __shared__ int stop;
+    __shared__ double sj_sh;
+    if (st->done || j >= st->k_limit) return;
+    const int tid = threadIdx.x, v = blockIdx.x, nv = gridDim.x;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int t = tid; t < rb.n_tiles; t += kBlock) acc = cadd(acc, rb.part[(size_t)v * rb.n_tiles + t]);
+    const double sx = block_sum(acc.x, lds);
+    const double sy = block_sum(acc.y, lds);
+    if (tid == 0) rb.red[v] = make_double2(sx, sy);
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) ticket = atomicAdd(rb.cnt, 1u);
+    __syncthreads();
+    if (ticket != (unsigned)(nv - 1)) return;
+    __threadfence();
+    for (int q = tid; q < nv; q += kBlock) sv[q] = rb.red[q];
+    if (tid == 0) {
+        *rb.cnt = 0u;
+        int halt = 0;
+        if (j == 0) {
+            if (st->norm_init) {  // column 0 is the raw v0
+                const double n2 = sv[1].x;
+                const double b0 = sqrt(n2);
+                st->beta0 = b0;
+                st->norm_init = 0;
+                if (!isfinite(n2)) {
+                    st->status = TE_ERR_NONFINITE;
+                    st->done = 1;
+                    halt = 1;
+                } else if (b0 == 0.0) {
+                    st->done = 1;
+                    halt = 1;
+                } else {
+                    st->s[0] = 1.0 / b0;
+                }
+            }
+        } else {
+            const double b = sqrt(sv[2 * j + 1].x);  // ||V[:, j]|| = beta_{j-1}
+            st->beta[j - 1] = b;
+            if (!isfinite(b)) {
+                st->status = TE_ERR_NONFINITE;
+                st->done = 1;
+                halt = 1;
+            } else if (b < st->p.tol_rate) {  // lucky breakdown (Alg. 1: no < tol_rate)
+                st->k_limit = j;
+                st->breakdown = 1;
+                st->h = b;
+                halt = 1;
+            } else {
+                st->s[j] = 1.0 / b;
+            }
+        }
+        stop = halt;
+        sj_sh = st->s[j];
     }
     __threadfence_block();
     __syncthreads();
-    // two sweeps of c <- c' - E c with E = G - I
-    for (int sweep = 0; sweep < 2; ++sweep) {
-        double2 acc = make_double2(0.0, 0.0);
-        if (tid <= j) {
-            acc = (sweep == 0) ? cp[tid] : c1[tid];
-            double2 corr = make_double2(0.0, 0.0);
-            for (int l = 0; l <= j; ++l) {
-                double2 e = st->G[tid * kMaxM + l];
-                if (l == tid) e.x -= 1.0;
-                corr = cfma(e, (sweep == 0) ? cp[l] : c1[l], corr);
-            }
-            acc.x = cp[tid].x - corr.x;
-            acc.y = cp[tid].y - corr.y;
-        }
-        __syncthreads();
-        if (tid <= j) c1[tid] = acc;
-        __syncthreads();
-    }
+    if (stop) return;
+    const double sj = sj_sh;
     if (tid <= j) {
-        const double2 c = c1[tid];
+        const double sc = st->s[tid] * sj;
+        cp[tid] = cscale(sv[2 * tid], sc);    // c'_i = v_i^H y
+        g[tid] = cscale(sv[2 * tid + 1], sc); // g_i  = v_i^H v_j
+    }
+    __syncthreads();
+    double2 gnew = make_double2(0.0, 0.0);
+    if (tid <= j) {
+        double2 e = g[tid];
+        if (tid == j) e.x -= 1.0;
+        double2 c = cfms(e, cp[j], cp[tid]);
+        if (j >= 1) {
+            double2 f;
+            if (tid < j) {
+                f = st->gprev[tid];
+                if (tid == j - 1) f.x -= 1.0;
+            } else {
+                f = cconj(g[j - 1]);
+            }
+            c = cfms(f, cp[j - 1], c);
+        }
         st->ceff[tid] = cscale(c, st->s[tid]);
         if (tid == j) {
             st->alpha[j] = c.x;
+            st->ys = sj;
             if (!isfinite(c.x) || !isfinite(c.y)) {
                 st->status = TE_ERR_NONFINITE;
                 st->done = 1;
             }
         }
+        gnew = g[tid];
     }
+    __syncthreads();  // every gprev read above precedes the overwrite
+    if (tid <= j) st->gprev[tid] = gnew;
 }
 
-// ------------------------------------------------------------- pass B: update + norm
+// ----------------------------------------------------------------- update: new column
 template <int RPT>
 __global__ __launch_bounds__(kBlock) void k_update(double2* __restrict__ V, int64_t ld, int dim, int j,
-                                                    const double2* __restrict__ y, DevState* __restrict__ st,
+                                                    const double2* __restrict__ y, const DevState* __restrict__ st,
                                                     RedBuf rb) {
     __shared__ double lds[kWaves];
-    __shared__ double2 vals[1];
     if (st->done || j >= st->k_limit) return;
     const int tid = threadIdx.x;
     const int r0 = blockIdx.x * (kBlock * RPT);
-    const bool store = (j + 1) < st->p.m;
+    const bool last = (j + 1) == st->p.m;
+    const double ys = st->ys;
     double2 p[RPT];
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
         const int r = r0 + tid + q * kBlock;
-        p[q] = (r < dim) ? y[r] : make_double2(0.0, 0.0);
+        p[q] = (r < dim) ? cscale(y[r], ys) : make_double2(0.0, 0.0);
     }
     for (int i = 0; i <= j; ++i) {
         const double2 c = st->ceff[i];
@@ -248,46 +301,28 @@ __global__ __launch_bounds__(kBlock) void k_update(double2* __restrict__ V, int6
             if (r < dim) p[q] = cfms(c, vi[r], p[q]);
         }
     }
-    double acc = 0.0;
-    double2* __restrict__ vn = V + (int64_t)(j + 1) * ld;
+    if (!last) {
+        double2* __restrict__ vn = V + (int64_t)(j + 1) * ld;
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-        const int r = r0 + tid + q * kBlock;
-        if (r < dim) {
-            if (store) vn[r] = p[q];
+        for (int q = 0; q < RPT; ++q) {
+            const int r = r0 + tid + q * kBlock;
+            if (r < dim) vn[r] = p[q];
+        }
+    } else {  // the last residual is not stored; its norm is h of eq. errorIntegral
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
             acc = fma(p[q].x, p[q].x, acc);
             acc = fma(p[q].y, p[q].y, acc);
         }
+        const double s = block_sum(acc, lds);
+        if (tid == 0) rb.npart[blockIdx.x] = s;
     }
-    {
-        const int lane = tid & 63, wave = tid >> 6;
-        const double s = wave_sum(acc);
-        if (lane == 0) lds[wave] = s;
-        __syncthreads();
-        if (tid == 0) {
-            double b = 0.0;
-            for (int w = 0; w < kWaves; ++w) b += lds[w];
-            vals[0] = make_double2(b, 0.0);
-        }
-        __syncthreads();
-    }
-    if (!grid_reduce(vals, 1, blockIdx.x, rb)) return;
-    if (tid == 0) {
-        const double beta = sqrt(vals[0].x);
-        st->beta[j] = beta;
-        if (!isfinite(beta)) {
-            st->status = TE_ERR_NONFINITE;
-            st->done = 1;
-        } else if (beta < st->p.tol_rate) {  // lucky breakdown (Alg. 1: no < tol_rate)
-            st->k_limit = j + 1;
-            st->breakdown = 1;
-            st->h = beta;
-        } else if (j + 1 == st->p.m) {
-            st->h = beta;
-        } else {
-            st->s[j + 1] = 1.0 / beta;
-        }
-    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_last_norm(DevState* st, RedBuf rb) {
+    __shared__ double lds[kWaves];
+    finish_last_norm(st, rb, lds);
 }
 
 // ------------------------------------------------------------- recombination w = V omega
@@ -337,10 +372,8 @@ __global__ __launch_bounds__(kBlock) void k_output(const double2* __restrict__ V
 template <int G>
 __global__ __launch_bounds__(kBlock) void k_spmv(const int* __restrict__ rp, const int* __restrict__ ci,
                                                   const double2* __restrict__ val, const double2* __restrict__ x,
-                                                  double2* __restrict__ y, int dim, DevState* __restrict__ st,
-                                                  RedBuf rb, int rows_per_tile) {
-    __shared__ double2 wpart[kWaves];
-    __shared__ double2 vals[1];
+                                                  double2* __restrict__ y, int dim, RedBuf rb, int rows_per_tile) {
+    __shared__ double lds[kWaves];
     const int tid = threadIdx.x, lg = tid % G, grp = tid / G;
     const int r0 = blockIdx.x * rows_per_tile;
     const int r1 = min(r0 + rows_per_tile, dim);
@@ -358,18 +391,19 @@ __global__ __launch_bounds__(kBlock) void k_spmv(const int* __restrict__ rp, con
             dot = cfma_conj(x[r], acc, dot);
         }
     }
-    dot.x = wave_sum(dot.x);
-    dot.y = wave_sum(dot.y);
-    if ((tid & 63) == 0) wpart[tid >> 6] = dot;
-    __syncthreads();
-    if (tid == 0) {
-        double2 s = make_double2(0.0, 0.0);
-        for (int w = 0; w < kWaves; ++w) s = cadd(s, wpart[w]);
-        vals[0] = s;
-    }
-    __syncthreads();
-    if (!grid_reduce(vals, 1, blockIdx.x, rb)) return;
-    if (tid == 0) st->ceff[0] = vals[0];
+    const double sx = block_sum(dot.x, lds);
+    const double sy = block_sum(dot.y, lds);
+    if (tid == 0) rb.part[blockIdx.x] = make_double2(sx, sy);
+}
+
+// one block: sum of rb.part[0..n_tiles) into st->ceff[0]
+__global__ __launch_bounds__(kBlock) void k_sum_part(DevState* st, RedBuf rb) {
+    __shared__ double lds[kWaves];
+    double2 acc = make_double2(0.0, 0.0);
+    for (int t = threadIdx.x; t < rb.n_tiles; t += kBlock) acc = cadd(acc, rb.part[t]);
+    const double sx = block_sum(acc.x, lds);
+    const double sy = block_sum(acc.y, lds);
+    if (threadIdx.x == 0) st->ceff[0] = make_double2(sx, sy);
 }
 
 // ------------------------------------------------------------------ CSR validation
@@ -400,8 +434,8 @@ __global__ __launch_bounds__(kBlock) void k_validate(const int* __restrict__ rp,
         sum += hypot(v.x, v.y);
         if (check_herm) {
             if (k > kb && ci[k - 1] >= c) e |= 8;
-            // binary search column r in row c (sorted columns required)
-            // clamp: row c's own pointers may be invalid (reported by that row's thread)
+            // binary search column r in row c (sorted columns required); clamp: row c's own
+            // pointers may be invalid (reported by that row's thread)
             int lo = max(rp[c], 0), hi = (int)min((int64_t)rp[c + 1], nnz) - 1;
             bool found = false;
             double2 w = make_double2(0.0, 0.0);
@@ -444,72 +478,83 @@ __global__ __launch_bounds__(kBlock) void k_max(const double* __restrict__ a, in
 // --------------------------------------------------------------------------- launchers
 template <typename F>
 static hipError_t by_rpt(int rpt, F&& f) {
-    switch (rpt) {
-        case 1: f(std::integral_constant<int, 1>{}); break;
-        case 2: f(std::integral_constant<int, 2>{}); break;
-        case 4: f(std::integral_constant<int, 4>{}); break;
-        default: f(std::integral_constant<int, 8>{}); break;
-    }
+    if (rpt == 1) f(std::integral_constant<int, 1>{});
+    else f(std::integral_constant<int, 2>{});
     return hipGetLastError();
 }
 
-hipError_t launch_init(const Tiling& tl, const double2* v0, double2* V, int dim, DevState* st,
-                       const RedBuf& rb, const Problem& prob, hipStream_t s) {
-    return by_rpt(tl.rpt, [&](auto r) {
-        k_init<decltype(r)::value><<<tl.n_tiles, kBlock, 0, s>>>(v0, V, dim, st, rb, prob);
-    });
+static int grid_for(int dim) { return (int)std::min<int64_t>(((int64_t)dim + kBlock - 1) / kBlock, 4096); }
+
+hipError_t launch_setup(DevState* st, const Problem& prob, hipStream_t s) {
+    k_setup<<<1, 64, 0, s>>>(st, prob);
+    return hipGetLastError();
 }
 
-hipError_t launch_project(const Tiling& tl, const Csr& H, double2* V, int64_t ld, int j, double2* y,
-                          DevState* st, const RedBuf& rb, hipStream_t s) {
+hipError_t launch_copy(const double2* src, double2* dst, int dim, hipStream_t s) {
+    k_copy<<<grid_for(dim), kBlock, 0, s>>>(src, dst, dim);
+    return hipGetLastError();
+}
+
+hipError_t launch_project(const Tiling& tl, const Csr& H, const double2* V, int64_t ld, int j, double2* y,
+                          const DevState* st, const RedBuf& rb, hipStream_t s) {
     return by_rpt(tl.rpt, [&](auto r) {
         k_project<decltype(r)::value, 4><<<tl.n_tiles, kBlock, 0, s>>>(H.row_ptr, H.col, H.val, V, ld, H.dim, j, y,
                                                                         st, rb);
     });
 }
 
+hipError_t launch_reduce(int j, DevState* st, const RedBuf& rb, hipStream_t s) {
+    k_reduce<<<2 * (j + 1), kBlock, 0, s>>>(st, rb, j);
+    return hipGetLastError();
+}
+
 hipError_t launch_update(const Tiling& tl, double2* V, int64_t ld, int dim, int j, const double2* y,
-                         DevState* st, const RedBuf& rb, hipStream_t s) {
+                         const DevState* st, const RedBuf& rb, hipStream_t s) {
     return by_rpt(tl.rpt, [&](auto r) {
         k_update<decltype(r)::value><<<tl.n_tiles, kBlock, 0, s>>>(V, ld, dim, j, y, st, rb);
     });
 }
 
-hipError_t launch_combine(const Tiling& tl, double2* V, int64_t ld, int dim, DevState* st, hipStream_t s) {
+hipError_t launch_last_norm(DevState* st, const RedBuf& rb, hipStream_t s) {
+    k_last_norm<<<1, kBlock, 0, s>>>(st, rb);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(const Tiling& tl, double2* V, int64_t ld, int dim, const DevState* st, hipStream_t s) {
     return by_rpt(tl.rpt, [&](auto r) {
         k_combine<decltype(r)::value><<<tl.n_tiles, kBlock, 0, s>>>(V, ld, dim, st);
     });
 }
 
-hipError_t launch_output(const Tiling&, const double2* V, double2* out, int dim, const DevState* st, hipStream_t s) {
-    const int blocks = (int)std::min<int64_t>(((int64_t)dim + kBlock - 1) / kBlock, 4096);
-    hipLaunchKernelGGL(k_output, dim3(blocks), dim3(kBlock), 0, s, V, out, dim, st);
+hipError_t launch_output(const double2* V, double2* out, int dim, const DevState* st, hipStream_t s) {
+    k_output<<<grid_for(dim), kBlock, 0, s>>>(V, out, dim, st);
     return hipGetLastError();
 }
 
 hipError_t launch_scale_columns(const double2* src, double2* dst, int64_t ld, int dim, int k, const DevState* st,
                                 hipStream_t s) {
     const int bx = (int)std::min<int64_t>(((int64_t)dim + kBlock - 1) / kBlock, 1024);
-    hipLaunchKernelGGL(k_scale_columns, dim3(bx, std::max(1, std::min(k, 64))), dim3(kBlock), 0, s, src, dst, ld, dim, k, st);
+    k_scale_columns<<<dim3(bx, std::max(1, std::min(k, 64))), kBlock, 0, s>>>(src, dst, ld, dim, k, st);
     return hipGetLastError();
 }
 
 hipError_t launch_spmv_only(const Tiling& tl, const Csr& H, const double2* x, double2* y, DevState* st,
                             const RedBuf& rb, hipStream_t s) {
-    hipLaunchKernelGGL(k_spmv<4>, dim3(tl.n_tiles), dim3(kBlock), 0, s, H.row_ptr, H.col, H.val, x, y, H.dim, st, rb,
-                       tl.rows);
+    k_spmv<4><<<tl.n_tiles, kBlock, 0, s>>>(H.row_ptr, H.col, H.val, x, y, H.dim, rb, tl.rows);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_sum_part<<<1, kBlock, 0, s>>>(st, rb);
     return hipGetLastError();
 }
 
 hipError_t launch_validate(const Csr& H, int check_hermitian, int* err, double* rowsum, hipStream_t s) {
     const int blocks = (H.dim + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(k_validate, dim3(blocks), dim3(kBlock), 0, s, H.row_ptr, H.col, H.val, H.dim, H.nnz,
-                       check_hermitian, err, rowsum);
+    k_validate<<<blocks, kBlock, 0, s>>>(H.row_ptr, H.col, H.val, H.dim, H.nnz, check_hermitian, err, rowsum);
     return hipGetLastError();
 }
 
 hipError_t launch_norm1(const double* rowsum, int dim, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_max, dim3(1), dim3(kBlock), 0, s, rowsum, dim, out);
+    k_max<<<1, kBlock, 0, s>>>(rowsum, dim, out);
     return hipGetLastError();
 }
 

@@ -426,7 +426,11 @@ __device__ void step_body(DevState* st, int* host_flag, bool controller) {
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_step(DevState* st, int* host_flag) { step_body(st, host_flag, true); }
+__global__ __launch_bounds__(kBlock) void k_step(DevState* st, RedBuf rb, int* host_flag) {
+    __shared__ double lds[kWaves];
+    finish_last_norm(st, rb, lds);  // h of a build that ran all m iterations
+    step_body(st, host_flag, true);
+}
 
 // step search alone on a state prepared by the host (component entry point)
 __global__ __launch_bounds__(kBlock) void k_step_only(DevState* st) { step_body(st, nullptr, false); }
@@ -470,8 +474,8 @@ __global__ __launch_bounds__(kBlock) void k_integral_only(int k, const double* l
 
 }  // namespace
 
-hipError_t launch_step(DevState* st, int* host_flag, hipStream_t s) {
-    hipLaunchKernelGGL(k_step, dim3(1), dim3(kBlock), 0, s, st, host_flag);
+hipError_t launch_step(DevState* st, const RedBuf& rb, int* host_flag, hipStream_t s) {
+    hipLaunchKernelGGL(k_step, dim3(1), dim3(kBlock), 0, s, st, rb, host_flag);
     return hipGetLastError();
 }
 

@@ -25,7 +25,7 @@ struct Problem {
 };
 
 struct DevState {
-    Problem p;  // set by the init kernel
+    Problem p;  // set by the setup kernel
     double beta0;
     // progress
     double t_now, tau_prev, err_acc, num_acc;
@@ -35,30 +35,38 @@ struct DevState {
     int32_t k_limit;   // iterations j < k_limit still run (m, or k after a breakdown)
     int32_t breakdown; // lucky breakdown in this build
     int32_t k_comb;    // columns the recombination uses
-    int32_t pad0;
+    int32_t norm_init; // column 0 is the raw v0: take s[0] = 1/||column 0|| at the next projection
     double h;          // residual norm h_{k+1,k}
+    double ys;         // scale of the raw product y = H V[:, j] (s[j])
     double last_tau, last_err;
     double alpha[kMaxM];
     double beta[kMaxM];
-    double s[kMaxM + 1];      // column scales: normalised v_i = s[i] * V[:, i]
-    double2 ceff[kMaxM];      // orthogonalisation coefficients on the raw columns
-    double2 omega[kMaxM];     // recombination coefficients on the raw columns
-    double2 G[kMaxM * kMaxM]; // Gram matrix of the normalised basis, G[i*kMaxM + j]
+    double s[kMaxM + 1];        // column scales: normalised v_i = s[i] * V[:, i]
+    double2 ceff[kMaxM];        // orthogonalisation coefficients on the raw columns
+    double2 omega[kMaxM];       // recombination coefficients on the raw columns
+    double2 gprev[kMaxM + 1];   // Gram column v_i^H v_{j-1} of the previous iteration
 };
 
-// Scratch of the deterministic two-level grid reduction: tiles write partials, the last
-// tile of each group of kGroup folds its group, the last group folds the groups.
+// Reduction scratch: every tile of a row-parallel kernel writes its partial sums with plain
+// stores; a later kernel folds them in a fixed order (the kernel boundary orders the memory
+// traffic, so no device-scope fence runs inside the streaming kernels).
 struct RedBuf {
-    double2* part;   // [kMaxVals][n_tiles]
-    double2* gpart;  // [kMaxVals][n_groups]
-    unsigned* gcnt;  // [n_groups], zero between kernels
-    unsigned* fcnt;  // [1], zero between kernels
-    int n_tiles, n_groups;
+    double2* part;   // [kMaxVals][n_tiles] projection partials
+    double* npart;   // [n_tiles] squared-norm partials of the last residual
+    double2* red;    // [kMaxVals] folded projection values
+    unsigned* cnt;   // ticket of the fold kernel, zero between kernels
+    int n_tiles;
 };
 
 // -------------------------------------------------------------------- complex helpers
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+// a*b
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+}
 // acc + a*b
 __device__ __forceinline__ double2 cfma(double2 a, double2 b, double2 acc) {
     acc.x = fma(a.x, b.x, acc.x);
@@ -90,92 +98,16 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Sums `nv` values that every thread of the block holds in vals[] (identical layout),
-// result in out[] (LDS, visible to all threads after return).  Fixed order.
-template <int NV>
-__device__ __forceinline__ void block_sum(const double (&vals)[NV], double* out, double* lds /* kWaves*NV */) {
+// Block-wide sum in a fixed order; every thread gets the result.
+__device__ __forceinline__ double block_sum(double v, double* lds /* kWaves */) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        double s = wave_sum(vals[v]);
-        if (lane == 0) lds[wave * NV + v] = s;
-    }
+    v = wave_sum(v);
     __syncthreads();
-    if (threadIdx.x < NV) {
-        double s = 0.0;
-        for (int w = 0; w < kWaves; ++w) s += lds[w * NV + threadIdx.x];
-        out[threadIdx.x] = s;
-    }
+    if (lane == 0) lds[wave] = v;
     __syncthreads();
-}
-
-// Two-level deterministic grid reduction of `nv` complex values per tile.  Every block
-// calls it with its tile partials in `vals` (LDS).  Returns true in exactly one block
-// (the last to arrive), which then holds the grid totals in `vals`.
-__device__ inline bool grid_reduce(double2* vals, int nv, int tile, const RedBuf& rb) {
-    __shared__ unsigned ticket;
-    __shared__ double2 tmp[kBlock];
-    const int tid = threadIdx.x;
-    for (int v = tid; v < nv; v += kBlock) rb.part[(size_t)v * rb.n_tiles + tile] = vals[v];
-    __threadfence();
-    __syncthreads();
-    const int group = tile / kGroup;
-    const int g0 = group * kGroup;
-    const int gs = min(kGroup, rb.n_tiles - g0);
-    if (tid == 0) ticket = atomicAdd(&rb.gcnt[group], 1u);
-    __syncthreads();
-    if (ticket != (unsigned)(gs - 1)) return false;
-    __threadfence();
-    // fold this group's gs tiles: thread -> (value, stripe), fixed order
-    {
-        const int stripes = max(1, min(gs, kBlock / max(nv, 1)));
-        for (int v0 = 0; v0 < nv; v0 += kBlock / stripes) {
-            const int v = v0 + tid % (kBlock / stripes);
-            const int st = tid / (kBlock / stripes);
-            double2 acc = make_double2(0.0, 0.0);
-            if (v < nv && st < stripes) {
-                for (int t = st; t < gs; t += stripes) acc = cadd(acc, rb.part[(size_t)v * rb.n_tiles + g0 + t]);
-            }
-            tmp[tid] = acc;
-            __syncthreads();
-            if (tid < kBlock / stripes && v0 + tid < nv) {
-                double2 s = make_double2(0.0, 0.0);
-                for (int q = 0; q < stripes; ++q) s = cadd(s, tmp[q * (kBlock / stripes) + tid]);
-                rb.gpart[(size_t)(v0 + tid) * rb.n_groups + group] = s;
-            }
-            __syncthreads();
-        }
-    }
-    if (tid == 0) rb.gcnt[group] = 0u;
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) ticket = atomicAdd(rb.fcnt, 1u);
-    __syncthreads();
-    if (ticket != (unsigned)(rb.n_groups - 1)) return false;
-    __threadfence();
-    {
-        const int ng = rb.n_groups;
-        const int stripes = max(1, min(ng, kBlock / max(nv, 1)));
-        for (int v0 = 0; v0 < nv; v0 += kBlock / stripes) {
-            const int v = v0 + tid % (kBlock / stripes);
-            const int st = tid / (kBlock / stripes);
-            double2 acc = make_double2(0.0, 0.0);
-            if (v < nv && st < stripes) {
-                for (int g = st; g < ng; g += stripes) acc = cadd(acc, rb.gpart[(size_t)v * ng + g]);
-            }
-            tmp[tid] = acc;
-            __syncthreads();
-            if (tid < kBlock / stripes && v0 + tid < nv) {
-                double2 s = make_double2(0.0, 0.0);
-                for (int q = 0; q < stripes; ++q) s = cadd(s, tmp[q * (kBlock / stripes) + tid]);
-                vals[v0 + tid] = s;
-            }
-            __syncthreads();
-        }
-    }
-    if (tid == 0) *rb.fcnt = 0u;
-    __syncthreads();
-    return true;
+    double s = 0.0;
+    for (int w = 0; w < kWaves; ++w) s += lds[w];
+    return s;
 }
 
 // ----------------------------------------------------------------------- launchers
@@ -195,22 +127,24 @@ struct Tiling {
     int g;        // lanes per row in the sparse product
     int rows;     // rows per tile = kBlock * rpt
     int n_tiles;
-    int n_groups;
 };
 Tiling choose_tiling(int dim);
 
-hipError_t launch_init(const Tiling& tl, const double2* v0, double2* V, int dim, DevState* st,
-                       const RedBuf& rb, const Problem& prob, hipStream_t s);
-hipError_t launch_project(const Tiling& tl, const Csr& H, double2* V, int64_t ld, int j, double2* y,
-                          DevState* st, const RedBuf& rb, hipStream_t s);
+hipError_t launch_setup(DevState* st, const Problem& prob, hipStream_t s);
+hipError_t launch_copy(const double2* src, double2* dst, int dim, hipStream_t s);
+hipError_t launch_project(const Tiling& tl, const Csr& H, const double2* V, int64_t ld, int j, double2* y,
+                          const DevState* st, const RedBuf& rb, hipStream_t s);
+hipError_t launch_reduce(int j, DevState* st, const RedBuf& rb, hipStream_t s);
 hipError_t launch_update(const Tiling& tl, double2* V, int64_t ld, int dim, int j, const double2* y,
-                         DevState* st, const RedBuf& rb, hipStream_t s);
-hipError_t launch_combine(const Tiling& tl, double2* V, int64_t ld, int dim, DevState* st, hipStream_t s);
-hipError_t launch_output(const Tiling& tl, const double2* V, double2* out, int dim, const DevState* st,
-                         hipStream_t s);
-hipError_t launch_step(DevState* st, int* host_flag, hipStream_t s);
+                         const DevState* st, const RedBuf& rb, hipStream_t s);
+hipError_t launch_last_norm(DevState* st, const RedBuf& rb, hipStream_t s);
+hipError_t launch_combine(const Tiling& tl, double2* V, int64_t ld, int dim, const DevState* st, hipStream_t s);
+hipError_t launch_output(const double2* V, double2* out, int dim, const DevState* st, hipStream_t s);
+hipError_t launch_step(DevState* st, const RedBuf& rb, int* host_flag, hipStream_t s);
 hipError_t launch_spmv_only(const Tiling& tl, const Csr& H, const double2* x, double2* y, DevState* st,
                             const RedBuf& rb, hipStream_t s);
+hipError_t launch_scale_columns(const double2* src, double2* dst, int64_t ld, int dim, int k, const DevState* st,
+                                hipStream_t s);
 hipError_t launch_validate(const Csr& H, int check_hermitian, int* err, double* rowsum, hipStream_t s);
 hipError_t launch_norm1(const double* rowsum, int dim, double* out, hipStream_t s);
 
@@ -220,5 +154,27 @@ hipError_t launch_eig_only(int k, const double* alpha, const double* beta, doubl
 hipError_t launch_integral_only(int k, const double* lambda, const double* coef, double h, double a, double b,
                                 const Problem& opt, double* out, hipStream_t s);
 hipError_t launch_step_only(DevState* st, hipStream_t s);
+
+// Whole block: fold the squared-norm partials of the last residual (iteration m-1) into
+// h = ||p|| and test it for a lucky breakdown.  No-op when a breakdown already set k < m.
+__device__ inline void finish_last_norm(DevState* st, const RedBuf& rb, double* lds) {
+    if (st->done || st->breakdown) return;
+    double acc = 0.0;
+    for (int t = threadIdx.x; t < rb.n_tiles; t += kBlock) acc += rb.npart[t];
+    const double h2 = block_sum(acc, lds);
+    if (threadIdx.x == 0) {
+        const double h = sqrt(h2);
+        st->beta[st->p.m - 1] = h;
+        st->h = h;
+        if (!isfinite(h)) {
+            st->status = TE_ERR_NONFINITE;
+            st->done = 1;
+        } else if (h < st->p.tol_rate) {
+            st->breakdown = 1;
+        }
+    }
+    __threadfence_block();
+    __syncthreads();
+}
 
 }  // namespace te

@@ -50,11 +50,11 @@ class te_result(ctypes.Structure):
 
 
 TE_OPT_PROFILE = 1
-KERNEL_CLASSES = ("project", "update", "step", "combine")
+KERNEL_CLASSES = ("project", "update", "step", "combine", "fold")
 
 
 class te_profile(ctypes.Structure):
-    _fields_ = [("launches", ctypes.c_int64 * 4), ("seconds", ctypes.c_double * 4), ("bytes", ctypes.c_double * 4)]
+    _fields_ = [("launches", ctypes.c_int64 * 5), ("seconds", ctypes.c_double * 5), ("bytes", ctypes.c_double * 5)]
 
     def as_dict(self):
         return {name: {"launches": int(self.launches[i]), "seconds": float(self.seconds[i]),
