@@ -95,8 +95,8 @@ struct Workspace {
         *off_npart = o;
         o += (size_t)tl.n_tiles * sizeof(double);
         o = align_up(o, 256);
-        *off_red = o;  // folded values, then the fold ticket
-        o += (size_t)kMaxVals * sizeof(double2) + 256;
+        *off_red = o;  // folded values
+        o += (size_t)kMaxVals * sizeof(double2);
         o = align_up(o, 256);
         *off_st = o;
         o += sizeof(DevState);
@@ -156,14 +156,13 @@ te_status make_workspace(te_hamiltonian h, int m, Workspace** out) {
     w->rb.part = (double2*)(w->base + op);
     w->rb.npart = (double*)(w->base + on);
     w->rb.red = (double2*)(w->base + orr);
-    w->rb.cnt = (unsigned*)(w->base + orr + (size_t)kMaxVals * sizeof(double2));
     w->rb.n_tiles = w->tl.n_tiles;
     w->st = (DevState*)(w->base + os);
     te_status rc = TE_OK;
     auto chk = [&](hipError_t e, const char* what) {
         if (e != hipSuccess && rc == TE_OK) rc = fail(TE_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
     };
-    chk(hipMemset(w->rb.cnt, 0, 256), "hipMemset");
+    chk(hipMemset(w->rb.red, 0, (size_t)kMaxVals * sizeof(double2)), "hipMemset");
     chk(hipMemset(w->st, 0, sizeof(DevState)), "hipMemset");
     chk(hipHostMalloc((void**)&w->host_flag, 64, hipHostMallocMapped | hipHostMallocCoherent), "hipHostMalloc");
     if (rc == TE_OK) chk(hipHostGetDevicePointer((void**)&w->host_flag_dev, w->host_flag, 0), "hipHostGetDevicePointer");
@@ -184,7 +183,7 @@ hipError_t enqueue_restart(te_hamiltonian h, Workspace* w, hipStream_t s) {
     hipError_t e = hipSuccess;
     for (int j = 0; j < w->m && e == hipSuccess; ++j) {
         e = launch_project(w->tl, h->csr, w->V, w->ld, j, w->y, w->st, w->rb, s);
-        if (e == hipSuccess) e = launch_reduce(j, w->st, w->rb, s);
+        if (e == hipSuccess) e = launch_fold(j, w->st, w->rb, s);
         if (e == hipSuccess) e = launch_update(w->tl, w->V, w->ld, w->dim, j, w->y, w->st, w->rb, s);
     }
     if (e == hipSuccess) e = launch_step(w->st, w->rb, w->host_flag_dev, s);
@@ -200,7 +199,7 @@ hipError_t enqueue_restart_profiled(te_hamiltonian h, Workspace* w, hipStream_t 
     for (int j = 0; j < w->m && e == hipSuccess; ++j) {
         e = launch_project(w->tl, h->csr, w->V, w->ld, j, w->y, w->st, w->rb, s);
         if (e == hipSuccess) e = hipEventRecord(E[3 * j + 1], s);
-        if (e == hipSuccess) e = launch_reduce(j, w->st, w->rb, s);
+        if (e == hipSuccess) e = launch_fold(j, w->st, w->rb, s);
         if (e == hipSuccess) e = hipEventRecord(E[3 * j + 2], s);
         if (e == hipSuccess) e = launch_update(w->tl, w->V, w->ld, w->dim, j, w->y, w->st, w->rb, s);
         if (e == hipSuccess) e = hipEventRecord(E[3 * j + 3], s);
@@ -523,6 +522,22 @@ te_status te_evolve(te_hamiltonian h, const te_c128* v0, te_c128* v_out, double 
         return fail(hs.status, "device-side failure (eigensolver did not converge)");
     }
     if (hs.beta0 == 0.0 && res) res->t_reached = t;
+    if (std::getenv("TE_TRACE")) {
+        DevState* full = new (std::nothrow) DevState();
+        if (full && hipMemcpy(full, w->st, sizeof(DevState), hipMemcpyDeviceToHost) == hipSuccess) {
+            const int n = std::min(hs.steps, kTrace);
+            std::fprintf(stderr, "[te trace] restarts=%d matvecs=%d bound=%.3e status=%d\n", hs.steps, hs.matvecs,
+                         hs.err_acc, hs.status);
+            for (int q = std::max(0, hs.steps - n); q < hs.steps; ++q) {
+                const double* tr = full->trace[q % kTrace];
+                std::fprintf(stderr, "[te trace] %3d t_now=%.6f tau=%.6f err=%.3e h=%.3e k=%d bd=%d qok=%d t_rem=%.6f\n", q,
+                             tr[0], tr[1], tr[2], tr[3], (int)tr[4], (int)tr[5], (int)tr[6], tr[7]);
+            }
+        }
+        delete full;
+    }
+    if (hs.beta0 != 0.0 && hs.t_now != t)
+        return fail(TE_ERR_DEVICE, "evolution stopped at t=" + std::to_string(hs.t_now) + " before reaching t");
     return TE_OK;
 }
 
@@ -577,7 +592,7 @@ te_status te_arnoldi(te_hamiltonian h, const te_c128* u, int32_t m, double tol_r
     TE_HIP(launch_copy((const double2*)u, w->V, dim, s));
     for (int j = 0; j < mm; ++j) {
         TE_HIP(launch_project(w->tl, h->csr, w->V, w->ld, j, w->y, w->st, w->rb, s));
-        TE_HIP(launch_reduce(j, w->st, w->rb, s));
+        TE_HIP(launch_fold(j, w->st, w->rb, s));
         TE_HIP(launch_update(w->tl, w->V, w->ld, dim, j, w->y, w->st, w->rb, s));
     }
     TE_HIP(launch_last_norm(w->st, w->rb, s));

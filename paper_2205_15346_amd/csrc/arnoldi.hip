@@ -173,79 +173,94 @@ __global__ __launch_bounds__(kBlock) void k_project(const int* __restrict__ rp, 
 }
 
 // ---------------------------------------------------- fold of the projection partials
-// Block v folds value v over all tiles (fixed order); the last block to finish applies the
-// scales, the breakdown test and the Gram correction.
-__global__ __launch_bounds__(kBlock) void k_reduce(DevState* __restrict__ st, RedBuf rb, int j) {
+// Block v folds value v over all tiles in a fixed order.
+__global__ __launch_bounds__(kBlock) void k_fold(const DevState* __restrict__ st, RedBuf rb, int j) {
     __shared__ double lds[kWaves];
-    __shared__ double2 sv[kMaxVals];
-    __shared__ double2 cp[kMaxM + 1], g[kMaxM + 1];
-    __shared__ unsigned ticket;
-    __shared__ int stop;
-    __shared__ double sj_sh;
     if (st->done || j >= st->k_limit) return;
-    const int tid = threadIdx.x, v = blockIdx.x, nv = gridDim.x;
+    const int v = blockIdx.x;
     double2 acc = make_double2(0.0, 0.0);
-    for (int t = tid; t < rb.n_tiles; t += kBlock) acc = cadd(acc, rb.part[(size_t)v * rb.n_tiles + t]);
+    for (int t = threadIdx.x; t < rb.n_tiles; t += kBlock) acc = cadd(acc, rb.part[(size_t)v * rb.n_tiles + t]);
     const double sx = block_sum(acc.x, lds);
     const double sy = block_sum(acc.y, lds);
-    if (tid == 0) rb.red[v] = make_double2(sx, sy);
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) ticket = atomicAdd(rb.cnt, 1u);
-    __syncthreads();
-    if (ticket != (unsigned)(nv - 1)) return;
-    __threadfence();
-    for (int q = tid; q < nv; q += kBlock) sv[q] = rb.red[q];
+    if (threadIdx.x == 0) rb.red[v] = make_double2(sx, sy);
+}
+
+// ----------------------------------------------------------------- update: new column
+// Prologue (every block, identical arithmetic; block 0 also records the state):
+//   ||V[:, j]|| = sqrt(g_j raw) is beta_{j-1} (or ||v0|| at the first projection) -> breakdown
+//   test and s_j; c'_i = s_i s_j (V_i^H y)_raw, g_i = s_i s_j (V_i^H V_j)_raw;
+//   c_i = c'_i - E_{i,j} c'_j - E_{i,j-1} c'_{j-1}, E = G - I, column j-1 of G from iteration j-1.
+// Body: V[:, j+1] = s_j y - sum_i c_i s_i V[:, i]; the last residual only yields its norm.
+template <int RPT>
+__global__ __launch_bounds__(kBlock) void k_update(double2* __restrict__ V, int64_t ld, int dim, int j,
+                                                    const double2* __restrict__ y, DevState* __restrict__ st,
+                                                    RedBuf rb) {
+    __shared__ double lds[kWaves];
+    __shared__ double2 cp[kMaxM + 1], g[kMaxM + 1], cs[kMaxM + 1];
+    __shared__ double sj_sh;
+    __shared__ int stop_sh;
+    if (st->done || j >= st->k_limit) return;
+    const int tid = threadIdx.x;
+    const bool rec = blockIdx.x == 0;
     if (tid == 0) {
-        *rb.cnt = 0u;
-        int halt = 0;
+        int stop = 0;
+        double sj;
         if (j == 0) {
-            if (st->norm_init) {  // column 0 is the raw v0
-                const double n2 = sv[1].x;
+            sj = st->s[0];
+            if (st->norm_init) {  // column 0 holds the raw v0
+                const double n2 = rb.red[1].x;
                 const double b0 = sqrt(n2);
-                st->beta0 = b0;
-                st->norm_init = 0;
                 if (!isfinite(n2)) {
-                    st->status = TE_ERR_NONFINITE;
-                    st->done = 1;
-                    halt = 1;
+                    stop = 1;
+                    if (rec) {
+                        st->status = TE_ERR_NONFINITE;
+                        st->done = 1;
+                    }
                 } else if (b0 == 0.0) {
-                    st->done = 1;
-                    halt = 1;
+                    stop = 1;
+                    if (rec) st->done = 1;
                 } else {
-                    st->s[0] = 1.0 / b0;
+                    sj = 1.0 / b0;
+                }
+                if (rec) {  // norm_init itself is cleared by the step kernel: other blocks read it
+                    st->beta0 = b0;
+                    st->s[0] = sj;
                 }
             }
         } else {
-            const double b = sqrt(sv[2 * j + 1].x);  // ||V[:, j]|| = beta_{j-1}
-            st->beta[j - 1] = b;
+            const double b = sqrt(rb.red[2 * j + 1].x);  // ||V[:, j]|| = beta_{j-1}
+            sj = 1.0 / b;
+            if (rec) st->beta[j - 1] = b;
             if (!isfinite(b)) {
-                st->status = TE_ERR_NONFINITE;
-                st->done = 1;
-                halt = 1;
+                stop = 1;
+                if (rec) {
+                    st->status = TE_ERR_NONFINITE;
+                    st->done = 1;
+                }
             } else if (b < st->p.tol_rate) {  // lucky breakdown (Alg. 1: no < tol_rate)
-                st->k_limit = j;
-                st->breakdown = 1;
-                st->h = b;
-                halt = 1;
-            } else {
-                st->s[j] = 1.0 / b;
+                stop = 1;
+                if (rec) {
+                    st->k_limit = j;
+                    st->breakdown = 1;
+                    st->h = b;
+                }
+            } else if (rec) {
+                st->s[j] = sj;
             }
         }
-        stop = halt;
-        sj_sh = st->s[j];
+        sj_sh = sj;
+        stop_sh = stop;
     }
-    __threadfence_block();
     __syncthreads();
-    if (stop) return;
+    if (stop_sh) return;
     const double sj = sj_sh;
     if (tid <= j) {
-        const double sc = st->s[tid] * sj;
-        cp[tid] = cscale(sv[2 * tid], sc);    // c'_i = v_i^H y
-        g[tid] = cscale(sv[2 * tid + 1], sc); // g_i  = v_i^H v_j
+        const double si = (tid == j) ? sj : st->s[tid];
+        const double sc = si * sj;
+        cp[tid] = cscale(rb.red[2 * tid], sc);     // c'_i = v_i^H y
+        g[tid] = cscale(rb.red[2 * tid + 1], sc);  // g_i  = v_i^H v_j
     }
     __syncthreads();
-    double2 gnew = make_double2(0.0, 0.0);
     if (tid <= j) {
         double2 e = g[tid];
         if (tid == j) e.x -= 1.0;
@@ -253,47 +268,38 @@ __global__ __launch_bounds__(kBlock) void k_reduce(DevState* __restrict__ st, Re
         if (j >= 1) {
             double2 f;
             if (tid < j) {
-                f = st->gprev[tid];
+                f = st->gcol[(j - 1) & 1][tid];
                 if (tid == j - 1) f.x -= 1.0;
             } else {
                 f = cconj(g[j - 1]);
             }
             c = cfms(f, cp[j - 1], c);
         }
-        st->ceff[tid] = cscale(c, st->s[tid]);
-        if (tid == j) {
-            st->alpha[j] = c.x;
-            st->ys = sj;
-            if (!isfinite(c.x) || !isfinite(c.y)) {
-                st->status = TE_ERR_NONFINITE;
-                st->done = 1;
+        const double si = (tid == j) ? sj : st->s[tid];
+        cs[tid] = cscale(c, si);
+        if (rec) {
+            st->gcol[j & 1][tid] = g[tid];
+            if (tid == j) {
+                st->alpha[j] = c.x;
+                if (!isfinite(c.x) || !isfinite(c.y)) {
+                    st->status = TE_ERR_NONFINITE;
+                    st->done = 1;
+                }
             }
         }
-        gnew = g[tid];
     }
-    __syncthreads();  // every gprev read above precedes the overwrite
-    if (tid <= j) st->gprev[tid] = gnew;
-}
+    __syncthreads();
 
-// ----------------------------------------------------------------- update: new column
-template <int RPT>
-__global__ __launch_bounds__(kBlock) void k_update(double2* __restrict__ V, int64_t ld, int dim, int j,
-                                                    const double2* __restrict__ y, const DevState* __restrict__ st,
-                                                    RedBuf rb) {
-    __shared__ double lds[kWaves];
-    if (st->done || j >= st->k_limit) return;
-    const int tid = threadIdx.x;
     const int r0 = blockIdx.x * (kBlock * RPT);
     const bool last = (j + 1) == st->p.m;
-    const double ys = st->ys;
     double2 p[RPT];
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
         const int r = r0 + tid + q * kBlock;
-        p[q] = (r < dim) ? cscale(y[r], ys) : make_double2(0.0, 0.0);
+        p[q] = (r < dim) ? cscale(y[r], sj) : make_double2(0.0, 0.0);
     }
     for (int i = 0; i <= j; ++i) {
-        const double2 c = st->ceff[i];
+        const double2 c = cs[i];
         const double2* __restrict__ vi = V + (int64_t)i * ld;
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
@@ -503,13 +509,13 @@ hipError_t launch_project(const Tiling& tl, const Csr& H, const double2* V, int6
     });
 }
 
-hipError_t launch_reduce(int j, DevState* st, const RedBuf& rb, hipStream_t s) {
-    k_reduce<<<2 * (j + 1), kBlock, 0, s>>>(st, rb, j);
+hipError_t launch_fold(int j, const DevState* st, const RedBuf& rb, hipStream_t s) {
+    k_fold<<<2 * (j + 1), kBlock, 0, s>>>(st, rb, j);
     return hipGetLastError();
 }
 
 hipError_t launch_update(const Tiling& tl, double2* V, int64_t ld, int dim, int j, const double2* y,
-                         const DevState* st, const RedBuf& rb, hipStream_t s) {
+                         DevState* st, const RedBuf& rb, hipStream_t s) {
     return by_rpt(tl.rpt, [&](auto r) {
         k_update<decltype(r)::value><<<tl.n_tiles, kBlock, 0, s>>>(V, ld, dim, j, y, st, rb);
     });

@@ -410,7 +410,19 @@ __device__ void step_body(DevState* st, int* host_flag, bool controller) {
             tn = P.t;
         }
         st->t_now = tn;
+        {
+            double* tr = st->trace[(st->steps - 1) % kTrace];
+            tr[0] = t_now;
+            tr[1] = so.tau;
+            tr[2] = so.err;
+            tr[3] = h;
+            tr[4] = (double)k;
+            tr[5] = (double)breakdown;
+            tr[6] = (double)so.quad_ok;
+            tr[7] = t_rem;
+        }
         st->k_comb = k;
+        st->norm_init = 0;
         st->do_combine = 1;
         st->s[0] = 1.0;
         if (tn >= P.t) st->done = 1;

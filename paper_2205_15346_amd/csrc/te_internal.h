@@ -13,6 +13,8 @@ constexpr int kWaves = kBlock / 64;
 constexpr int kMaxM = TE_MAX_KRYLOV;
 constexpr int kGroup = 16;       // tiles per first-level reduction group
 constexpr int kMaxVals = 2 * (kMaxM + 1);  // values one tile contributes to a reduction
+constexpr int kTrace = 64;                 // restarts kept in the device trace ring
+constexpr int kTraceFields = 8;            // t_now, tau, err, h, k, breakdown, quad_ok, t_rem
 
 // ---------------------------------------------------------------------------------------
 // Solver state kept in device memory for one evolution.  Written only by the single
@@ -44,17 +46,17 @@ struct DevState {
     double s[kMaxM + 1];        // column scales: normalised v_i = s[i] * V[:, i]
     double2 ceff[kMaxM];        // orthogonalisation coefficients on the raw columns
     double2 omega[kMaxM];       // recombination coefficients on the raw columns
-    double2 gprev[kMaxM + 1];   // Gram column v_i^H v_{j-1} of the previous iteration
+    double2 gcol[2][kMaxM + 1]; // Gram column v_i^H v_j of iteration j in gcol[j & 1]
+    double trace[kTrace][kTraceFields];  // restart r in row r % kTrace
 };
 
 // Reduction scratch: every tile of a row-parallel kernel writes its partial sums with plain
-// stores; a later kernel folds them in a fixed order (the kernel boundary orders the memory
-// traffic, so no device-scope fence runs inside the streaming kernels).
+// stores and a later kernel folds them in a fixed order.  All cross-workgroup communication
+// goes through kernel boundaries: no atomics or device-scope fences on the hot path.
 struct RedBuf {
     double2* part;   // [kMaxVals][n_tiles] projection partials
     double* npart;   // [n_tiles] squared-norm partials of the last residual
     double2* red;    // [kMaxVals] folded projection values
-    unsigned* cnt;   // ticket of the fold kernel, zero between kernels
     int n_tiles;
 };
 
@@ -134,9 +136,9 @@ hipError_t launch_setup(DevState* st, const Problem& prob, hipStream_t s);
 hipError_t launch_copy(const double2* src, double2* dst, int dim, hipStream_t s);
 hipError_t launch_project(const Tiling& tl, const Csr& H, const double2* V, int64_t ld, int j, double2* y,
                           const DevState* st, const RedBuf& rb, hipStream_t s);
-hipError_t launch_reduce(int j, DevState* st, const RedBuf& rb, hipStream_t s);
+hipError_t launch_fold(int j, const DevState* st, const RedBuf& rb, hipStream_t s);
 hipError_t launch_update(const Tiling& tl, double2* V, int64_t ld, int dim, int j, const double2* y,
-                         const DevState* st, const RedBuf& rb, hipStream_t s);
+                         DevState* st, const RedBuf& rb, hipStream_t s);
 hipError_t launch_last_norm(DevState* st, const RedBuf& rb, hipStream_t s);
 hipError_t launch_combine(const Tiling& tl, double2* V, int64_t ld, int dim, const DevState* st, hipStream_t s);
 hipError_t launch_output(const double2* V, double2* out, int dim, const DevState* st, hipStream_t s);
