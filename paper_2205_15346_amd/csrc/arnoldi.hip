@@ -68,18 +68,25 @@ __global__ __launch_bounds__(kBlock) void k_copy(const double2* __restrict__ src
 // -------------------------------------------------------------- project: SpMV + projections
 // Cross-lane reduction of 32 doubles per lane (8 columns x {Re, Im} x {y, x}): five halving
 // exchanges leave value (lane >> 1) in lanes 2q and 2q+1 after a last pairwise exchange;
-// 32 shuffles instead of 192 for independent butterflies.
-__device__ __forceinline__ double halving_reduce32(double (&a)[32], int lane) {
+// 32 shuffles instead of 192 for independent butterflies.  Every index is a compile-time
+// constant so the array stays in registers.
+template <int H>
+__device__ __forceinline__ void halve(double (&a)[32], int lane) {
+    const bool hi = (lane & (2 * H)) != 0;
 #pragma unroll
-    for (int h = 16, o = 32; h >= 1; h >>= 1, o >>= 1) {
-        const bool hi = (lane & o) != 0;
-#pragma unroll
-        for (int v = 0; v < h; ++v) {
-            const double send = hi ? a[v] : a[v + h];
-            const double keep = hi ? a[v + h] : a[v];
-            a[v] = keep + __shfl_xor(send, o);
-        }
+    for (int v = 0; v < H; ++v) {
+        const double send = hi ? a[v] : a[v + H];
+        const double keep = hi ? a[v + H] : a[v];
+        a[v] = keep + __shfl_xor(send, 2 * H);
     }
+}
+
+__device__ __forceinline__ double halving_reduce32(double (&a)[32], int lane) {
+    halve<16>(a, lane);
+    halve<8>(a, lane);
+    halve<4>(a, lane);
+    halve<2>(a, lane);
+    halve<1>(a, lane);
     return a[0] + __shfl_xor(a[0], 1);
 }
 
