@@ -530,8 +530,11 @@ te_status te_evolve(te_hamiltonian h, const te_c128* v0, te_c128* v_out, double 
                          hs.err_acc, hs.status);
             for (int q = std::max(0, hs.steps - n); q < hs.steps; ++q) {
                 const double* tr = full->trace[q % kTrace];
-                std::fprintf(stderr, "[te trace] %3d t_now=%.6f tau=%.6f err=%.3e h=%.3e k=%d bd=%d qok=%d t_rem=%.6f\n", q,
-                             tr[0], tr[1], tr[2], tr[3], (int)tr[4], (int)tr[5], (int)tr[6], tr[7]);
+                std::fprintf(stderr,
+                             "[te trace] %3d t_now=%.6f tau=%.6f err=%.3e h=%.3e k=%d bd=%d qok=%d t_rem=%.6f "
+                             "eig_us=%.1f search_us=%.1f integrals=%d maxlev=%d\n",
+                             q, tr[0], tr[1], tr[2], tr[3], (int)tr[4], (int)tr[5], (int)tr[6], tr[7], tr[8], tr[9],
+                             (int)tr[10], (int)tr[11]);
             }
         }
         delete full;

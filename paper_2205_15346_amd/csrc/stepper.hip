@@ -17,91 +17,126 @@ namespace te {
 
 namespace {
 
-constexpr int QS = kMaxM + 1;  // padded row stride of Q in LDS
 constexpr double kEps = 2.220446049250313e-16;
 constexpr double kHalfPi = 1.5707963267948966;
+constexpr uint64_t kWallClockHz = 100000000ull;  // wall_clock64() runs at a constant 100 MHz on gfx9
+constexpr int kMaxTpn = 8;                       // threads sharing one quadrature node
 
 struct StepShared {
-    double Q[kMaxM * QS];
+    double Qt[kMaxM * 64];  // eigenvectors: column n (eigenvalue n) at Qt[n * 64 + row]
     double d[kMaxM], e[kMaxM];
     double lam[kMaxM], cf[kMaxM];
+    double pre[kBlock], pim[kBlock];
     double red[kWaves * 8];
+    double lev_sum[8];
     double bcast[8];
     int ibcast[4];
 };
 
 // ---------------------------------------------------------------- eigen-decomposition
-// Wave 0 only.  On return d[] holds the eigenvalues and column n of Q the eigenvector of
-// d[n].  Returns false if an eigenvalue needed more than 64 QL iterations.
-__device__ bool tridiag_ql(int k, double* d, double* e, double* Q) {
+// 1/sqrt(t) for t > 0: hardware estimate refined by one Newton step (relative error ~1 ulp).
+__device__ __forceinline__ double rsqrt_nr(double t) {
+    const double y = __builtin_amdgcn_rsq(t);
+    return y * fma(-0.5 * t * y, y, 1.5);
+}
+
+// Value of a wave-distributed register array at a wave-uniform lane index.
+__device__ __forceinline__ double lane_get(double x, int i) {
+    const long long v = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffffll), i);
+    const int hi = __builtin_amdgcn_readlane((int)(v >> 32), i);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Implicit QL with Wilkinson shifts on the k x k symmetric tridiagonal (diagonal a, off-diagonal
+// b), run by wave 0: lane i holds d_i and e_i in registers, lane q owns row q of the eigenvector
+// matrix (Qt, transposed in LDS).  Within a sweep every d/e value read is a pre-sweep value, so
+// the reads sit off the rotation chain; deflation points come from one ballot.  On return lam[]
+// holds the eigenvalues (unsorted) and Qt[n * 64 + q] = Q[q][n].  False if an eigenvalue needed
+// more than 64 iterations.
+__device__ bool tridiag_ql(int k, const double* a, const double* b, double* lam, double* Qt) {
     const int lane = threadIdx.x;  // < 64
-    for (int c = 0; c < k; ++c)
-        if (lane < k) Q[lane * QS + c] = (lane == c) ? 1.0 : 0.0;
-    e[k - 1] = 0.0;
+    double dr = (lane < k) ? a[lane] : 0.0;
+    double er = (lane < k - 1) ? b[lane] : 0.0;
+    for (int c = 0; c < k; ++c) Qt[c * 64 + lane] = (lane == c) ? 1.0 : 0.0;
     bool ok = true;
-    for (int l = 0; l < k; ++l) {
+    for (int l = 0; l < k && ok; ++l) {
         int iter = 0;
         while (true) {
-            int mm = l;
-            while (mm < k - 1) {
-                const double dd = fabs(d[mm]) + fabs(d[mm + 1]);
-                if (fabs(e[mm]) <= kEps * dd) break;
-                ++mm;
-            }
+            const double dn = __shfl_down(dr, 1);
+            const bool small = (lane >= k - 1) || (fabs(er) <= kEps * (fabs(dr) + fabs(dn)));
+            const unsigned long long mask = __ballot(small) & (~0ull << l);
+            const int mm = __ffsll((long long)mask) - 1;
             if (mm == l) break;
             if (++iter > 64) {
                 ok = false;
                 break;
             }
-            // Wilkinson shift from the leading 2x2 block
-            double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+            const double dl = lane_get(dr, l), el = lane_get(er, l);
+            double g = (lane_get(dr, l + 1) - dl) / (2.0 * el);
             double r = sqrt(fma(g, g, 1.0));
-            g = d[mm] - d[l] + e[l] / (g + copysign(r, g));
+            g = lane_get(dr, mm) - dl + el / (g + copysign(r, g));
+            // rotation chain in registers: lane i keeps (c_i, s_i) of the rotation in plane (i, i+1)
             double s = 1.0, c = 1.0, p = 0.0;
-            double carry = (lane < k) ? Q[lane * QS + mm] : 0.0;
+            double cr = 1.0, sr = 0.0;
             int i = mm - 1;
             bool underflow = false;
             for (; i >= l; --i) {
-                const double qi = (lane < k) ? Q[lane * QS + i] : 0.0;
-                const double f = s * e[i];
-                const double b = c * e[i];
-                r = sqrt(fma(f, f, g * g));
-                e[i + 1] = r;
-                if (r == 0.0) {
-                    d[i + 1] -= p;
-                    e[mm] = 0.0;
+                const double ei = lane_get(er, i), di = lane_get(dr, i), di1 = lane_get(dr, i + 1);
+                const double f = s * ei;
+                const double bb = c * ei;
+                const double t = fma(f, f, g * g);
+                if (t == 0.0) {
+                    if (lane == i + 1) dr = di1 - p;
+                    if (lane == mm) er = 0.0;
                     underflow = true;
                     break;
                 }
-                const double rinv = 1.0 / r;
+                const double rinv = rsqrt_nr(t);
+                if (lane == i + 1) er = t * rinv;
                 s = f * rinv;
                 c = g * rinv;
-                g = d[i + 1] - p;
-                r = (d[i] - g) * s + 2.0 * c * b;
-                p = s * r;
-                d[i + 1] = g + p;
-                g = c * r - b;
-                if (lane < k) {
-                    Q[lane * QS + i + 1] = s * qi + c * carry;
-                    carry = c * qi - s * carry;
+                if (lane == i) {
+                    cr = c;
+                    sr = s;
                 }
+                g = di1 - p;
+                r = (di - g) * s + 2.0 * c * bb;
+                p = s * r;
+                if (lane == i + 1) dr = g + p;
+                g = c * r - bb;
             }
-            if (underflow) {
-                if (lane < k) Q[lane * QS + i + 1] = carry;
-                continue;
+            // apply the rotations i = mm-1 .. lo to the columns of Q (lane = row)
+            const int lo = underflow ? i + 1 : l;
+            double carry = Qt[mm * 64 + lane];
+            for (int q = mm - 1; q >= lo; --q) {
+                const double cq = lane_get(cr, q), sq = lane_get(sr, q);
+                const double qi = Qt[q * 64 + lane];
+                Qt[(q + 1) * 64 + lane] = sq * qi + cq * carry;
+                carry = cq * qi - sq * carry;
             }
-            if (lane < k) Q[lane * QS + l] = carry;
-            d[l] -= p;
-            e[l] = g;
-            e[mm] = 0.0;
+            Qt[lo * 64 + lane] = carry;
+            if (underflow) continue;
+            if (lane == l) {
+                dr = dl - p;
+                er = g;
+            }
+            if (lane == mm) er = 0.0;
         }
-        if (!ok) break;
     }
+    if (lane < k) lam[lane] = dr;
     return ok;
 }
 
 // ------------------------------------------------------------------------- quadrature
-// node t of the flattened levels 0..5 (t < 193): level and abscissa u
+// node p (0 <= p < 3 * 2^lev) of refinement level lev >= 1: odd multiples of 2^-lev in (-3, 3)
+__device__ __forceinline__ double level_abscissa(int lev, int p) {
+    const int half = 3 * (1 << (lev - 1));
+    const double step = ldexp(1.0, -lev);
+    return (p < half) ? -(2.0 * (half - 1 - p) + 1.0) * step : (2.0 * (p - half) + 1.0) * step;
+}
+
+// node t of the flattened levels 0..L (t < 6 * 2^L + 1): level and abscissa u
 __device__ __forceinline__ void flat_node(int t, int* level, double* u) {
     if (t < 7) {
         *level = 0;
@@ -111,30 +146,8 @@ __device__ __forceinline__ void flat_node(int t, int* level, double* u) {
     int lev = 1;
     while (t >= 3 * (1 << (lev + 1)) + 1) ++lev;
     const int p = t - (3 * (1 << lev) + 1);
-    const int half = 3 * (1 << (lev - 1));
-    const double step = ldexp(1.0, -lev);
     *level = lev;
-    *u = (p < half) ? -(2.0 * (half - 1 - p) + 1.0) * step : (2.0 * (p - half) + 1.0) * step;
-}
-
-__device__ __forceinline__ double integrand(double x, int k, const double* lam, const double* cf, double h) {
-    double re = 0.0, im = 0.0;
-    for (int n = 0; n < k; ++n) {
-        double sn, cn;
-        sincos(lam[n] * x, &sn, &cn);
-        re = fma(cf[n], cn, re);
-        im = fma(-cf[n], sn, im);
-    }
-    return h * sqrt(fma(re, re, im * im));
-}
-
-__device__ __forceinline__ double node_value(double u, double center, double radius, int k, const double* lam,
-                                             const double* cf, double h) {
-    const double sh = kHalfPi * sinh(u);
-    const double x = center + radius * tanh(sh);
-    const double ch = cosh(sh);
-    const double w = radius * kHalfPi * cosh(u) / (ch * ch);
-    return w * integrand(x, k, lam, cf, h);
+    *u = level_abscissa(lev, p);
 }
 
 struct QuadOut {
@@ -143,89 +156,106 @@ struct QuadOut {
     int converged;
 };
 
+// Whole block.  Evaluates `count` nodes (abscissae from node_u(q) -> (u, level)), each shared
+// by tpn threads that split the k-term sum; leaves in sh.lev_sum[lev - lev0] the per-level sums
+// of w(u) f(x(u)) for levels lev0..lev0+nlev-1.  Fixed order.
+template <typename NodeFn>
+__device__ void eval_nodes(int count, int lev0, int nlev, NodeFn node_u, double center, double radius, int k,
+                           const double* lam, const double* cf, double h, StepShared& sh) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tpn = max(1, min(kMaxTpn, kBlock / max(count, 1)));
+    const int per_round = kBlock / tpn;
+    double acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+    for (int base = 0; base < count; base += per_round) {
+        const int node = base + tid / tpn, part = tid % tpn;
+        double re = 0.0, im = 0.0, w = 0.0;
+        int lev = -1;
+        if (node < count) {
+            double u;
+            node_u(node, &u, &lev);
+            const double shu = kHalfPi * sinh(u);
+            const double x = center + radius * tanh(shu);
+            const double ch = cosh(shu);
+            w = radius * kHalfPi * cosh(u) / (ch * ch);
+            for (int n = part; n < k; n += tpn) {
+                double sn, cn;
+                sincos(lam[n] * x, &sn, &cn);
+                re = fma(cf[n], cn, re);
+                im = fma(-cf[n], sn, im);
+            }
+        }
+        if (tpn > 1) {
+            sh.pre[tid] = re;
+            sh.pim[tid] = im;
+            __syncthreads();
+            if (part == 0 && node < count) {
+                for (int q = 1; q < tpn; ++q) {
+                    re += sh.pre[tid + q];
+                    im += sh.pim[tid + q];
+                }
+            }
+            __syncthreads();
+        }
+        if (part == 0 && node < count) {
+            const double val = w * h * sqrt(fma(re, re, im * im));
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (lev - lev0 == q) acc[q] += val;
+        }
+    }
+    for (int q = 0; q < nlev; ++q) {
+        const double s = wave_sum(acc[q]);
+        if (lane == 0) sh.red[wave * 8 + q] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < nlev) {
+        double t = 0.0;
+        for (int w = 0; w < kWaves; ++w) t += sh.red[w * 8 + threadIdx.x];
+        sh.lev_sum[threadIdx.x] = t;
+    }
+    __syncthreads();
+}
+
 // Whole block.  Integral of f over [a, b] by the adaptive tanh-sinh rule: stop at the first
 // level >= max(1, min_level) whose change is <= max(rel_tol |I|, noise_rate (b - a)).
-__device__ QuadOut integrate(double a, double b, const Problem& P, int k, const double* lam, const double* cf,
+// Levels 0..L1 (L1 = min(3, max_level), 49 nodes) are evaluated in one pass, later levels one
+// at a time.
+__device__ __noinline__ QuadOut integrate(double a, double b, const Problem& P, int k, const double* lam, const double* cf,
                              double h, double noise_rate, StepShared& sh) {
     QuadOut out;
-    if (b == a) {
-        out.value = 0.0;
-        out.level = 0;
-        out.converged = 1;
-        return out;
-    }
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    out.value = 0.0;
+    out.level = 0;
+    out.converged = 1;
+    if (b == a) return out;
     const double center = 0.5 * (a + b), radius = 0.5 * (b - a);
     const double abs_tol = noise_rate * (b - a);
-    const int L0 = min(5, P.quad_max_level);
-    const int n0 = 6 * (1 << L0) + 1;
-    // levels 0..L0 in one pass (<= 193 nodes <= blockDim)
-    double val = 0.0;
-    int my_level = -1;
-    if (tid < n0) {
-        double u;
-        flat_node(tid, &my_level, &u);
-        val = node_value(u, center, radius, k, lam, cf, h);
-    }
-    for (int lev = 0; lev <= L0; ++lev) {
-        const double s = wave_sum(my_level == lev ? val : 0.0);
-        if (lane == 0) sh.red[wave * 8 + lev] = s;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        double total = 0.0, prev = 0.0, value = 0.0;
-        int conv = 0, lev_out = L0;
-        for (int lev = 0; lev <= L0; ++lev) {
-            double ls = 0.0;
-            for (int w = 0; w < kWaves; ++w) ls += sh.red[w * 8 + lev];
-            total += ls;
-            value = total * ldexp(1.0, -lev);
-            if (lev >= 1 && lev >= P.quad_min_level && fabs(value - prev) <= fmax(P.quad_rel_tol * fabs(value), abs_tol)) {
-                conv = 1;
-                lev_out = lev;
-                break;
-            }
-            prev = value;
+    const int L1 = min(3, P.quad_max_level);
+    eval_nodes(6 * (1 << L1) + 1, 0, L1 + 1, [](int q, double* u, int* lev) { flat_node(q, lev, u); }, center, radius,
+               k, lam, cf, h, sh);
+    double total = 0.0, prev = 0.0, value = 0.0;
+    out.converged = 0;
+    for (int lev = 0; lev <= P.quad_max_level; ++lev) {
+        if (lev > L1) {
+            eval_nodes(3 * (1 << lev), lev, 1, [lev](int q, double* u, int* l) {
+                *u = level_abscissa(lev, q);
+                *l = lev;
+            }, center, radius, k, lam, cf, h, sh);
+            total += sh.lev_sum[0];
+            __syncthreads();
+        } else {
+            total += sh.lev_sum[lev];
         }
-        sh.bcast[0] = value;
-        sh.bcast[1] = total;
-        sh.bcast[2] = prev;
-        sh.ibcast[0] = conv;
-        sh.ibcast[1] = lev_out;
-    }
-    __syncthreads();
-    out.value = sh.bcast[0];
-    out.converged = sh.ibcast[0];
-    out.level = sh.ibcast[1];
-    double total = sh.bcast[1];
-    double prev = sh.bcast[0];
-    __syncthreads();
-    for (int lev = L0 + 1; !out.converged && lev <= P.quad_max_level; ++lev) {
-        const int n = 3 * (1 << lev), half = n / 2;
-        const double step = ldexp(1.0, -lev);
-        double acc = 0.0;
-        for (int p = tid; p < n; p += kBlock) {
-            const double u = (p < half) ? -(2.0 * (half - 1 - p) + 1.0) * step : (2.0 * (p - half) + 1.0) * step;
-            acc += node_value(u, center, radius, k, lam, cf, h);
-        }
-        const double s = wave_sum(acc);
-        if (lane == 0) sh.red[wave] = s;
-        __syncthreads();
-        if (tid == 0) {
-            double ls = 0.0;
-            for (int w = 0; w < kWaves; ++w) ls += sh.red[w];
-            sh.bcast[0] = ls;
-        }
-        __syncthreads();
-        total += sh.bcast[0];
-        const double value = total * step;
-        out.value = value;
+        value = total * ldexp(1.0, -lev);
         out.level = lev;
-        if (lev >= P.quad_min_level && fabs(value - prev) <= fmax(P.quad_rel_tol * fabs(value), abs_tol))
+        if (lev >= 1 && lev >= P.quad_min_level && fabs(value - prev) <= fmax(P.quad_rel_tol * fabs(value), abs_tol)) {
             out.converged = 1;
+            break;
+        }
         prev = value;
-        __syncthreads();
     }
+    out.value = value;
     return out;
 }
 
@@ -234,6 +264,8 @@ struct StepOut {
     double tau, err;
     int quad_ok;
     int underflow;
+    int integrals;
+    int max_level;
 };
 
 // Whole block; every thread returns the same result (decisions are taken on values
@@ -247,9 +279,13 @@ __device__ StepOut step_search(const Problem& P, int k, double h, int breakdown,
     StepOut o;
     o.quad_ok = 1;
     o.underflow = 0;
+    o.integrals = 0;
+    o.max_level = 0;
     auto I = [&](double a, double b) {
         QuadOut q = integrate(a, b, P, k, sh.lam, sh.cf, h, noise, sh);
         o.quad_ok &= q.converged;
+        o.integrals += 1;
+        o.max_level = max(o.max_level, q.level);
         return q.value;
     };
     if (breakdown) {
@@ -323,14 +359,11 @@ __device__ bool prepare_spectrum(const DevState* st, int k, StepShared& sh) {
     __syncthreads();
     __shared__ int ok_sh;
     if (tid < 64) {
-        const bool ok = tridiag_ql(k, sh.d, sh.e, sh.Q);
+        const bool ok = tridiag_ql(k, sh.d, sh.e, sh.lam, sh.Qt);
         if (tid == 0) ok_sh = ok ? 1 : 0;
     }
     __syncthreads();
-    if (tid < k) {
-        sh.lam[tid] = sh.d[tid];
-        sh.cf[tid] = sh.Q[(k - 1) * QS + tid] * sh.Q[tid];
-    }
+    if (tid < k) sh.cf[tid] = sh.Qt[tid * 64 + k - 1] * sh.Qt[tid * 64];
     __syncthreads();
     return ok_sh != 0;
 }
@@ -343,7 +376,7 @@ __device__ void write_omega(DevState* st, int k, double tau, bool scale_raw, Ste
         for (int n = 0; n < k; ++n) {
             double sn, cn;
             sincos(sh.lam[n] * tau, &sn, &cn);
-            const double a = sh.Q[tid * QS + n] * sh.Q[n];
+            const double a = sh.Qt[n * 64 + tid] * sh.Qt[n * 64];
             re = fma(a, cn, re);
             im = fma(-a, sn, im);
         }
@@ -368,7 +401,9 @@ __device__ void step_body(DevState* st, int* host_flag, bool controller) {
     const int breakdown = st->breakdown;
     const double t_now = st->t_now;
     const double t_rem = P.t - t_now;
+    const uint64_t c0 = wall_clock64();
     const bool ok = prepare_spectrum(st, k, sh);
+    const uint64_t c1 = wall_clock64();
     if (!ok) {
         if (tid == 0) {
             st->status = TE_ERR_DEVICE;
@@ -379,6 +414,7 @@ __device__ void step_body(DevState* st, int* host_flag, bool controller) {
         return;
     }
     const StepOut so = step_search(P, k, h, breakdown, st->first, st->tau_prev, t_rem, sh);
+    const uint64_t c2 = wall_clock64();
     if (so.underflow) {
         if (tid == 0) {
             st->status = TE_ERR_STEP_UNDERFLOW;
@@ -420,6 +456,11 @@ __device__ void step_body(DevState* st, int* host_flag, bool controller) {
             tr[5] = (double)breakdown;
             tr[6] = (double)so.quad_ok;
             tr[7] = t_rem;
+            const double tick_us = 1e6 / (double)kWallClockHz;
+            tr[8] = (double)(c1 - c0) * tick_us;
+            tr[9] = (double)(c2 - c1) * tick_us;
+            tr[10] = (double)so.integrals;
+            tr[11] = (double)so.max_level;
         }
         st->k_comb = k;
         st->norm_init = 0;
@@ -457,13 +498,13 @@ __global__ __launch_bounds__(kBlock) void k_eig_only(int k, const double* alpha,
     }
     __syncthreads();
     if (tid < 64) {
-        const bool ok = tridiag_ql(k, sh.d, sh.e, sh.Q);
+        const bool ok = tridiag_ql(k, sh.d, sh.e, sh.lam, sh.Qt);
         if (tid == 0) *status = ok ? 0 : 1;
     }
     __syncthreads();
     if (tid < k) {
-        lambda[tid] = sh.d[tid];
-        for (int n = 0; n < k; ++n) Q[n * k + tid] = sh.Q[tid * QS + n];  // column-major
+        lambda[tid] = sh.lam[tid];
+        for (int n = 0; n < k; ++n) Q[n * k + tid] = sh.Qt[n * 64 + tid];  // column-major
     }
 }
 

@@ -14,7 +14,8 @@ constexpr int kMaxM = TE_MAX_KRYLOV;
 constexpr int kGroup = 16;       // tiles per first-level reduction group
 constexpr int kMaxVals = 2 * (kMaxM + 1);  // values one tile contributes to a reduction
 constexpr int kTrace = 64;                 // restarts kept in the device trace ring
-constexpr int kTraceFields = 8;            // t_now, tau, err, h, k, breakdown, quad_ok, t_rem
+constexpr int kTraceFields = 12;  // t_now, tau, err, h, k, breakdown, quad_ok, t_rem,
+                                  // eigensolve us, step-search us, integrals, max level
 
 // ---------------------------------------------------------------------------------------
 // Solver state kept in device memory for one evolution.  Written only by the single
