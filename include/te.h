@@ -163,6 +163,26 @@ te_status te_evolve(te_hamiltonian h, const te_c128* v0, te_c128* v_out, double 
 te_status te_last_profile(te_hamiltonian h, te_profile* out);
 
 /* ---------------------------------------------------------------------------------------
+ * Autotuning of the kernel shapes (per Hamiltonian handle).  The projection kernel (sparse
+ * product fused with the projections) is timed on the handle's own matrix for every supported
+ * shape and the fastest is kept; te_evolve tunes a handle on first use unless the environment
+ * sets TE_AUTOTUNE=0.  If TE_TUNE_CACHE names a file, results are read from / appended to it
+ * (one line per "gfx950 dim nnz m" key). */
+typedef struct {
+    int32_t lanes_per_row;          /* lanes sharing one row of the sparse product: 4 or 8 */
+    int32_t nnz_per_lane;           /* nonzeros per lane in flight: 1 or 4 (4 lanes), 2 (8 lanes) */
+    int32_t rows_per_thread;        /* projection kernel: 1 or 2 */
+    int32_t update_rows_per_thread; /* update and recombination kernels: 1 or 2 */
+    double project_us;              /* measured time of one projection launch, 0 if not measured */
+} te_tuning;
+
+/* Times every supported projection shape for Krylov dimension m and keeps the fastest in h
+ * (out may be NULL).  Synchronous. */
+te_status te_autotune(te_hamiltonian h, int32_t m, te_tuning* out, void* stream);
+te_status te_get_tuning(te_hamiltonian h, te_tuning* out); /* the shape te_evolve will use */
+te_status te_set_tuning(te_hamiltonian h, const te_tuning* t); /* TE_ERR_INVALID_ARG if unsupported */
+
+/* ---------------------------------------------------------------------------------------
  * Component entry points: each runs one step of the hot path with the same kernels that
  * te_evolve uses, for testing and for callers that assemble their own loop.
  *

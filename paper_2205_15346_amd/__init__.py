@@ -9,7 +9,7 @@ Using any of the names below without a built library raises ImportError.
 import importlib
 
 _TE_NAMES = ("Hamiltonian", "TEError", "te_arnoldi", "te_default_options", "te_error_integral", "te_evolve",
-             "te_hamiltonian_create", "te_last_profile", "te_spmv", "te_step_search", "te_tridiag_eig",
+             "te_hamiltonian_create", "te_last_profile", "te_autotune", "te_get_tuning", "te_set_tuning", "te_spmv", "te_step_search", "te_tridiag_eig",
              "te_workspace_bytes")
 
 

@@ -90,10 +90,10 @@ struct Workspace {
         o += ld * sizeof(double2);
         o = align_up(o, 256);
         *off_part = o;
-        o += (size_t)kMaxVals * tl.n_tiles * sizeof(double2);
+        o += (size_t)kMaxVals * max_tiles(dim) * sizeof(double2);  // any tiling fits
         o = align_up(o, 256);
         *off_npart = o;
-        o += (size_t)tl.n_tiles * sizeof(double);
+        o += (size_t)max_tiles(dim) * sizeof(double);
         o = align_up(o, 256);
         *off_red = o;  // folded values
         o += (size_t)kMaxVals * sizeof(double2);
@@ -127,6 +127,8 @@ struct te_hamiltonian_s {
     std::mutex mu;
     Workspace* ws = nullptr;
     te_profile prof{};
+    bool tuned = false;        // tuning measured or set explicitly
+    te_tuning tuning{4, 4, 1, 1, 0.0};
     ~te_hamiltonian_s() {
         delete ws;
         dev_free(row_ptr);
@@ -137,13 +139,19 @@ struct te_hamiltonian_s {
 
 namespace {
 
+Tiling handle_tiling(te_hamiltonian h) {
+    if (!h->tuned) return default_tiling(h->csr.dim);
+    const te_tuning& t = h->tuning;
+    return make_tiling(h->csr.dim, t.rows_per_thread, t.lanes_per_row, t.nnz_per_lane, t.update_rows_per_thread);
+}
+
 te_status make_workspace(te_hamiltonian h, int m, Workspace** out) {
     auto* w = new (std::nothrow) Workspace();
     if (!w) return fail(TE_ERR_OUT_OF_MEMORY, "host allocation failed");
     w->dim = h->csr.dim;
     w->m = m;
     w->ld = (int64_t)align_up((size_t)w->dim, 64);
-    w->tl = choose_tiling(w->dim);
+    w->tl = handle_tiling(h);
     size_t oy, op, on, orr, os;
     w->bytes = Workspace::layout(w->dim, m, w->tl, &oy, &op, &on, &orr, &os);
     w->base = (char*)dev_alloc(w->bytes);
@@ -156,7 +164,8 @@ te_status make_workspace(te_hamiltonian h, int m, Workspace** out) {
     w->rb.part = (double2*)(w->base + op);
     w->rb.npart = (double*)(w->base + on);
     w->rb.red = (double2*)(w->base + orr);
-    w->rb.n_tiles = w->tl.n_tiles;
+    w->rb.n_tiles = w->tl.n_tiles_p;
+    w->rb.n_norm = w->tl.n_tiles_u;
     w->st = (DevState*)(w->base + os);
     te_status rc = TE_OK;
     auto chk = [&](hipError_t e, const char* what) {
@@ -277,23 +286,6 @@ te_status ensure_graph(te_hamiltonian h, Workspace* w) {
     return TE_OK;
 }
 
-te_status get_workspace(te_hamiltonian h, int m, Workspace** out) {
-    if (h->ws && h->ws->m == m) {
-        *out = h->ws;
-        return TE_OK;
-    }
-    delete h->ws;
-    h->ws = nullptr;
-    Workspace* w = nullptr;
-    te_status rc = make_workspace(h, m, &w);
-    if (rc != TE_OK) return rc;
-    h->ws = w;
-    rc = ensure_graph(h, w);
-    if (rc != TE_OK) return rc;
-    *out = w;
-    return TE_OK;
-}
-
 Problem make_problem(te_hamiltonian h, const te_options& o, double t, double tol, int m) {
     Problem p{};
     p.t = t;
@@ -309,6 +301,134 @@ Problem make_problem(te_hamiltonian h, const te_options& o, double t, double tol
     p.quad_min_level = o.quad_min_level;
     p.max_halvings = o.max_halvings;
     return p;
+}
+
+// re-point a workspace at a new tiling (the partial buffers fit every tiling)
+te_status retile(te_hamiltonian h, Workspace* w, const Tiling& t) {
+    w->tl = t;
+    w->rb.n_tiles = t.n_tiles_p;
+    w->rb.n_norm = t.n_tiles_u;
+    if (w->exec) {
+        (void)hipGraphExecDestroy(w->exec);
+        w->exec = nullptr;
+    }
+    if (w->graph) {
+        (void)hipGraphDestroy(w->graph);
+        w->graph = nullptr;
+    }
+    return ensure_graph(h, w);
+}
+
+std::string tune_key(te_hamiltonian h, int m) {
+    return "gfx950 " + std::to_string(h->csr.dim) + " " + std::to_string(h->csr.nnz) + " " + std::to_string(m);
+}
+
+bool tune_cache_lookup(const std::string& key, te_tuning* t) {
+    const char* path = std::getenv("TE_TUNE_CACHE");
+    if (!path || !*path) return false;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[256];
+    bool found = false;
+    while (std::fgets(line, sizeof(line), f)) {
+        char arch[32];
+        long long dim, nnz;
+        int m, g, u, rp, ru;
+        double us;
+        if (std::sscanf(line, "%31s %lld %lld %d %d %d %d %d %lf", arch, &dim, &nnz, &m, &g, &u, &rp, &ru, &us) != 9)
+            continue;
+        const std::string k = std::string(arch) + " " + std::to_string(dim) + " " + std::to_string(nnz) + " " +
+                              std::to_string(m);
+        if (k == key && tiling_supported(rp, g, u, ru)) {
+            *t = te_tuning{g, u, rp, ru, us};
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+void tune_cache_store(const std::string& key, const te_tuning& t) {
+    const char* path = std::getenv("TE_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s %d %d %d %d %.3f\n", key.c_str(), t.lanes_per_row, t.nnz_per_lane, t.rows_per_thread,
+                 t.update_rows_per_thread, t.project_us);
+    std::fclose(f);
+}
+
+// Times the projection kernel (iteration j = min(8, m-1), zero basis) for every supported shape.
+te_status run_autotune(te_hamiltonian h, Workspace* w, hipStream_t s) {
+    const std::string key = tune_key(h, w->m);
+    te_tuning best{};
+    if (tune_cache_lookup(key, &best)) {
+        h->tuning = best;
+        h->tuned = true;
+        return retile(h, w, handle_tiling(h));
+    }
+    const int J = std::min(8, w->m - 1);
+    te_options o;
+    te_default_options(&o);
+    const Problem prob = make_problem(h, o, 1.0, 1.0, w->m);
+    TE_HIP(hipMemsetAsync(w->V, 0, (size_t)(J + 1) * w->ld * sizeof(double2), s));
+    TE_HIP(launch_setup(w->st, prob, s));
+    hipEvent_t e0, e1;
+    TE_HIP(hipEventCreate(&e0));
+    TE_HIP(hipEventCreate(&e1));
+    const int rpt_u = default_tiling(w->dim).rpt_u;
+    const int shapes[3][2] = {{4, 1}, {4, 4}, {8, 2}};
+    double best_us = 1e30;
+    hipError_t err = hipSuccess;
+    for (int rp = 1; rp <= 2 && err == hipSuccess; ++rp) {
+        for (const auto& sh : shapes) {
+            const Tiling t = make_tiling(w->dim, rp, sh[0], sh[1], rpt_u);
+            RedBuf rb = w->rb;
+            rb.n_tiles = t.n_tiles_p;
+            err = launch_project(t, h->csr, w->V, w->ld, J, w->y, w->st, rb, s);
+            if (err == hipSuccess) err = hipEventRecord(e0, s);
+            for (int q = 0; q < 3 && err == hipSuccess; ++q) err = launch_project(t, h->csr, w->V, w->ld, J, w->y, w->st, rb, s);
+            if (err == hipSuccess) err = hipEventRecord(e1, s);
+            if (err == hipSuccess) err = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+            if (err != hipSuccess) break;
+            const double us = 1e3 * ms / 3.0;
+            if (us < best_us) {
+                best_us = us;
+                best = te_tuning{sh[0], sh[1], rp, rpt_u, us};
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return fail(TE_ERR_DEVICE, std::string("autotune: ") + hipGetErrorString(err));
+    h->tuning = best;
+    h->tuned = true;
+    tune_cache_store(key, best);
+    return retile(h, w, handle_tiling(h));
+}
+
+bool autotune_enabled() {
+    const char* v = std::getenv("TE_AUTOTUNE");
+    return !(v && v[0] == '0');
+}
+
+te_status get_workspace(te_hamiltonian h, int m, Workspace** out) {
+    if (h->ws && h->ws->m == m) {
+        *out = h->ws;
+        return TE_OK;
+    }
+    delete h->ws;
+    h->ws = nullptr;
+    Workspace* w = nullptr;
+    te_status rc = make_workspace(h, m, &w);
+    if (rc != TE_OK) return rc;
+    h->ws = w;
+    rc = ensure_graph(h, w);
+    if (rc != TE_OK) return rc;
+    *out = w;
+    return TE_OK;
 }
 
 te_status check_options(const te_options& o) {
@@ -366,7 +486,7 @@ size_t te_workspace_bytes(int64_t dim, int32_t m) {
     if (dim < 1 || dim >= (int64_t)1 << 31 || m < 1) return 0;
     const int mm = (int)std::min<int64_t>(m, dim);
     size_t a, b, c, d, e;
-    return Workspace::layout((int)dim, mm, choose_tiling((int)dim), &a, &b, &c, &d, &e);
+    return Workspace::layout((int)dim, mm, default_tiling((int)dim), &a, &b, &c, &d, &e);
 }
 
 te_status te_hamiltonian_create(te_hamiltonian* out, int64_t dim, int64_t nnz, const int32_t* row_ptr,
@@ -468,6 +588,10 @@ te_status te_evolve(te_hamiltonian h, const te_c128* v0, te_c128* v_out, double 
     Workspace* w = nullptr;
     rc = get_workspace(h, mm, &w);
     if (rc != TE_OK) return rc;
+    if (!h->tuned && autotune_enabled()) {
+        rc = run_autotune(h, w, s);
+        if (rc != TE_OK) return rc;
+    }
     const Problem prob = make_problem(h, o, t, tol, mm);
     volatile int* flag = (volatile int*)w->host_flag;
     for (int i = 0; i < 16; ++i) flag[i] = 0;
@@ -541,6 +665,42 @@ te_status te_evolve(te_hamiltonian h, const te_c128* v0, te_c128* v_out, double 
     }
     if (hs.beta0 != 0.0 && hs.t_now != t)
         return fail(TE_ERR_DEVICE, "evolution stopped at t=" + std::to_string(hs.t_now) + " before reaching t");
+    return TE_OK;
+}
+
+te_status te_autotune(te_hamiltonian h, int32_t m, te_tuning* out, void* stream) {
+    if (!h) return fail(TE_ERR_INVALID_ARG, "null handle");
+    if (m < 1 || m > TE_MAX_KRYLOV) return fail(TE_ERR_INVALID_ARG, "m out of range");
+    std::lock_guard<std::mutex> lock(h->mu);
+    Workspace* w = nullptr;
+    te_status rc = get_workspace(h, std::min<int>(m, h->csr.dim), &w);
+    if (rc != TE_OK) return rc;
+    h->tuned = false;
+    rc = run_autotune(h, w, (hipStream_t)stream);
+    if (rc == TE_OK && out) *out = h->tuning;
+    return rc;
+}
+
+te_status te_get_tuning(te_hamiltonian h, te_tuning* out) {
+    if (!h || !out) return fail(TE_ERR_INVALID_ARG, "null pointer");
+    std::lock_guard<std::mutex> lock(h->mu);
+    if (h->tuned) {
+        *out = h->tuning;
+    } else {
+        const Tiling t = default_tiling(h->csr.dim);
+        *out = te_tuning{t.g, t.u, t.rpt_p, t.rpt_u, 0.0};
+    }
+    return TE_OK;
+}
+
+te_status te_set_tuning(te_hamiltonian h, const te_tuning* t) {
+    if (!h || !t) return fail(TE_ERR_INVALID_ARG, "null pointer");
+    if (!tiling_supported(t->rows_per_thread, t->lanes_per_row, t->nnz_per_lane, t->update_rows_per_thread))
+        return fail(TE_ERR_INVALID_ARG, "unsupported tuning (lanes 4 with 1 or 4 nonzeros, lanes 8 with 2; rows 1 or 2)");
+    std::lock_guard<std::mutex> lock(h->mu);
+    h->tuning = *t;
+    h->tuned = true;
+    if (h->ws) return retile(h, h->ws, handle_tiling(h));
     return TE_OK;
 }
 

@@ -24,15 +24,29 @@
 
 namespace te {
 
-Tiling choose_tiling(int dim) {
+int max_tiles(int dim) { return (dim + kBlock - 1) / kBlock; }
+
+bool tiling_supported(int rpt_p, int g, int u, int rpt_u) {
+    const bool shape = (g == 4 && (u == 1 || u == 4)) || (g == 8 && u == 2);
+    return shape && (rpt_p == 1 || rpt_p == 2) && (rpt_u == 1 || rpt_u == 2);
+}
+
+Tiling make_tiling(int dim, int rpt_p, int g, int u, int rpt_u) {
     Tiling t;
-    // two rows per thread once that still leaves >= 1024 tiles (4 workgroups per CU);
-    // measured on MI355X: 1-2 rows per thread stream at ~6.5 TB/s, 8 rows per thread at ~3.9.
-    t.rpt = ((int64_t)dim >= (int64_t)kBlock * 2 * 1024) ? 2 : 1;
-    t.g = 4;
-    t.rows = kBlock * t.rpt;
-    t.n_tiles = (dim + t.rows - 1) / t.rows;
+    t.rpt_p = rpt_p;
+    t.g = g;
+    t.u = u;
+    t.n_tiles_p = (dim + kBlock * rpt_p - 1) / (kBlock * rpt_p);
+    t.rpt_u = rpt_u;
+    t.n_tiles_u = (dim + kBlock * rpt_u - 1) / (kBlock * rpt_u);
     return t;
+}
+
+// Without tuning: two rows per thread once that still leaves >= 1024 tiles (4 workgroups per
+// CU); measured on MI355X, 1-2 rows per thread stream at ~6.5 TB/s, 8 rows per thread at ~3.9.
+Tiling default_tiling(int dim) {
+    const int rpt = ((int64_t)dim >= (int64_t)kBlock * 2 * 1024) ? 2 : 1;
+    return make_tiling(dim, rpt, 4, 4, rpt);
 }
 
 // ------------------------------------------------------------------- setup / copy
@@ -90,7 +104,7 @@ __device__ __forceinline__ double halving_reduce32(double (&a)[32], int lane) {
     return a[0] + __shfl_xor(a[0], 1);
 }
 
-template <int RPT, int G>
+template <int RPT, int G, int U>
 __global__ __launch_bounds__(kBlock) void k_project(const int* __restrict__ rp, const int* __restrict__ ci,
                                                      const double2* __restrict__ val, const double2* __restrict__ V,
                                                      int64_t ld, int dim, int j, double2* __restrict__ y,
@@ -104,13 +118,30 @@ __global__ __launch_bounds__(kBlock) void k_project(const int* __restrict__ rp, 
     const int r1 = min(r0 + R, dim);
     const double2* __restrict__ x = V + (int64_t)j * ld;
 
-    // y = H V[:, j] (raw), G lanes per row streaming the CSR
+    // y = H V[:, j] (raw): G lanes per row stream the CSR, each with U nonzeros in flight
     {
         const int lg = tid % G, grp = tid / G;
         for (int r = r0 + grp; r < r1; r += kBlock / G) {
             double2 acc = make_double2(0.0, 0.0);
             const int kb = rp[r], ke = rp[r + 1];
-            for (int k = kb + lg; k < ke; k += G) acc = cfma(val[k], x[ci[k]], acc);
+            for (int k0 = kb + lg; k0 < ke; k0 += G * U) {
+                double2 vv[U];
+                int cc[U];
+#pragma unroll
+                for (int q = 0; q < U; ++q) {
+                    const int k = k0 + q * G;
+                    if (k < ke) {
+                        vv[q] = val[k];
+                        cc[q] = ci[k];
+                    } else {
+                        vv[q] = make_double2(0.0, 0.0);
+                        cc[q] = -1;
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < U; ++q)
+                    if (cc[q] >= 0) acc = cfma(vv[q], x[cc[q]], acc);
+            }
 #pragma unroll
             for (int o = G / 2; o > 0; o >>= 1) {
                 acc.x += __shfl_xor(acc.x, o);
@@ -510,9 +541,12 @@ hipError_t launch_copy(const double2* src, double2* dst, int dim, hipStream_t s)
 
 hipError_t launch_project(const Tiling& tl, const Csr& H, const double2* V, int64_t ld, int j, double2* y,
                           const DevState* st, const RedBuf& rb, hipStream_t s) {
-    return by_rpt(tl.rpt, [&](auto r) {
-        k_project<decltype(r)::value, 4><<<tl.n_tiles, kBlock, 0, s>>>(H.row_ptr, H.col, H.val, V, ld, H.dim, j, y,
-                                                                        st, rb);
+    return by_rpt(tl.rpt_p, [&](auto r) {
+        constexpr int RPT = decltype(r)::value;
+        const dim3 grid(tl.n_tiles_p), block(kBlock);
+        if (tl.g == 8) k_project<RPT, 8, 2><<<grid, block, 0, s>>>(H.row_ptr, H.col, H.val, V, ld, H.dim, j, y, st, rb);
+        else if (tl.u == 1) k_project<RPT, 4, 1><<<grid, block, 0, s>>>(H.row_ptr, H.col, H.val, V, ld, H.dim, j, y, st, rb);
+        else k_project<RPT, 4, 4><<<grid, block, 0, s>>>(H.row_ptr, H.col, H.val, V, ld, H.dim, j, y, st, rb);
     });
 }
 
@@ -523,8 +557,8 @@ hipError_t launch_fold(int j, const DevState* st, const RedBuf& rb, hipStream_t 
 
 hipError_t launch_update(const Tiling& tl, double2* V, int64_t ld, int dim, int j, const double2* y,
                          DevState* st, const RedBuf& rb, hipStream_t s) {
-    return by_rpt(tl.rpt, [&](auto r) {
-        k_update<decltype(r)::value><<<tl.n_tiles, kBlock, 0, s>>>(V, ld, dim, j, y, st, rb);
+    return by_rpt(tl.rpt_u, [&](auto r) {
+        k_update<decltype(r)::value><<<tl.n_tiles_u, kBlock, 0, s>>>(V, ld, dim, j, y, st, rb);
     });
 }
 
@@ -534,8 +568,8 @@ hipError_t launch_last_norm(DevState* st, const RedBuf& rb, hipStream_t s) {
 }
 
 hipError_t launch_combine(const Tiling& tl, double2* V, int64_t ld, int dim, const DevState* st, hipStream_t s) {
-    return by_rpt(tl.rpt, [&](auto r) {
-        k_combine<decltype(r)::value><<<tl.n_tiles, kBlock, 0, s>>>(V, ld, dim, st);
+    return by_rpt(tl.rpt_u, [&](auto r) {
+        k_combine<decltype(r)::value><<<tl.n_tiles_u, kBlock, 0, s>>>(V, ld, dim, st);
     });
 }
 
@@ -553,7 +587,7 @@ hipError_t launch_scale_columns(const double2* src, double2* dst, int64_t ld, in
 
 hipError_t launch_spmv_only(const Tiling& tl, const Csr& H, const double2* x, double2* y, DevState* st,
                             const RedBuf& rb, hipStream_t s) {
-    k_spmv<4><<<tl.n_tiles, kBlock, 0, s>>>(H.row_ptr, H.col, H.val, x, y, H.dim, rb, tl.rows);
+    k_spmv<4><<<tl.n_tiles_p, kBlock, 0, s>>>(H.row_ptr, H.col, H.val, x, y, H.dim, rb, kBlock * tl.rpt_p);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_sum_part<<<1, kBlock, 0, s>>>(st, rb);

@@ -76,47 +76,40 @@ __device__ bool tridiag_ql(int k, const double* a, const double* b, double* lam,
             double g = (lane_get(dr, l + 1) - dl) / (2.0 * el);
             double r = sqrt(fma(g, g, 1.0));
             g = lane_get(dr, mm) - dl + el / (g + copysign(r, g));
-            // rotation chain in registers: lane i keeps (c_i, s_i) of the rotation in plane (i, i+1)
             double s = 1.0, c = 1.0, p = 0.0;
-            double cr = 1.0, sr = 0.0;
+            double carry = Qt[mm * 64 + lane];
             int i = mm - 1;
-            bool underflow = false;
+            int underflow = 0;
             for (; i >= l; --i) {
                 const double ei = lane_get(er, i), di = lane_get(dr, i), di1 = lane_get(dr, i + 1);
+                const double qi = Qt[i * 64 + lane];
                 const double f = s * ei;
                 const double bb = c * ei;
                 const double t = fma(f, f, g * g);
-                if (t == 0.0) {
+                // wave-uniform test as a scalar branch
+                if (__builtin_amdgcn_readfirstlane((int)(t == 0.0))) {
                     if (lane == i + 1) dr = di1 - p;
                     if (lane == mm) er = 0.0;
-                    underflow = true;
+                    underflow = 1;
                     break;
                 }
                 const double rinv = rsqrt_nr(t);
                 if (lane == i + 1) er = t * rinv;
                 s = f * rinv;
                 c = g * rinv;
-                if (lane == i) {
-                    cr = c;
-                    sr = s;
-                }
                 g = di1 - p;
                 r = (di - g) * s + 2.0 * c * bb;
                 p = s * r;
                 if (lane == i + 1) dr = g + p;
                 g = c * r - bb;
+                Qt[(i + 1) * 64 + lane] = s * qi + c * carry;
+                carry = c * qi - s * carry;
             }
-            // apply the rotations i = mm-1 .. lo to the columns of Q (lane = row)
-            const int lo = underflow ? i + 1 : l;
-            double carry = Qt[mm * 64 + lane];
-            for (int q = mm - 1; q >= lo; --q) {
-                const double cq = lane_get(cr, q), sq = lane_get(sr, q);
-                const double qi = Qt[q * 64 + lane];
-                Qt[(q + 1) * 64 + lane] = sq * qi + cq * carry;
-                carry = cq * qi - sq * carry;
+            if (underflow) {
+                Qt[(i + 1) * 64 + lane] = carry;
+                continue;
             }
-            Qt[lo * 64 + lane] = carry;
-            if (underflow) continue;
+            Qt[l * 64 + lane] = carry;
             if (lane == l) {
                 dr = dl - p;
                 er = g;

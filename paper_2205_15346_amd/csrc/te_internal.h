@@ -58,7 +58,8 @@ struct RedBuf {
     double2* part;   // [kMaxVals][n_tiles] projection partials
     double* npart;   // [n_tiles] squared-norm partials of the last residual
     double2* red;    // [kMaxVals] folded projection values
-    int n_tiles;
+    int n_tiles;     // tiles of the projection kernel (rows of part)
+    int n_norm;      // tiles of the update kernel (entries of npart)
 };
 
 // -------------------------------------------------------------------- complex helpers
@@ -124,14 +125,21 @@ struct Csr {
     int64_t nnz;
 };
 
-// Row tiling of the row-parallel kernels.
+// Row tiling of the row-parallel kernels.  The projection kernel's shape is chosen per matrix
+// by the autotuner: g lanes share a row of the sparse product, each keeping u nonzeros in
+// flight, and every thread owns rpt_p rows of the dense passes.
 struct Tiling {
-    int rpt;      // rows per thread
-    int g;        // lanes per row in the sparse product
-    int rows;     // rows per tile = kBlock * rpt
-    int n_tiles;
+    int rpt_p;      // rows per thread, projection kernel (1 or 2)
+    int g;          // lanes per row in the sparse product (4 or 8)
+    int u;          // nonzeros per lane in flight (1, 2 or 4)
+    int n_tiles_p;  // tiles (workgroups) of the projection kernel
+    int rpt_u;      // rows per thread, update and recombination kernels (1 or 2)
+    int n_tiles_u;
 };
-Tiling choose_tiling(int dim);
+Tiling make_tiling(int dim, int rpt_p, int g, int u, int rpt_u);
+Tiling default_tiling(int dim);
+bool tiling_supported(int rpt_p, int g, int u, int rpt_u);
+int max_tiles(int dim);  // tiles of the finest tiling (rpt = 1): sizes the partial buffers
 
 hipError_t launch_setup(DevState* st, const Problem& prob, hipStream_t s);
 hipError_t launch_copy(const double2* src, double2* dst, int dim, hipStream_t s);
@@ -163,7 +171,7 @@ hipError_t launch_step_only(DevState* st, hipStream_t s);
 __device__ inline void finish_last_norm(DevState* st, const RedBuf& rb, double* lds) {
     if (st->done || st->breakdown) return;
     double acc = 0.0;
-    for (int t = threadIdx.x; t < rb.n_tiles; t += kBlock) acc += rb.npart[t];
+    for (int t = threadIdx.x; t < rb.n_norm; t += kBlock) acc += rb.npart[t];
     const double h2 = block_sum(acc, lds);
     if (threadIdx.x == 0) {
         const double h = sqrt(h2);

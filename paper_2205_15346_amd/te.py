@@ -61,6 +61,15 @@ class te_profile(ctypes.Structure):
                        "bytes": float(self.bytes[i])} for i, name in enumerate(KERNEL_CLASSES)}
 
 
+class te_tuning(ctypes.Structure):
+    _fields_ = [("lanes_per_row", ctypes.c_int32), ("nnz_per_lane", ctypes.c_int32),
+                ("rows_per_thread", ctypes.c_int32), ("update_rows_per_thread", ctypes.c_int32),
+                ("project_us", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 class TEError(RuntimeError):
     def __init__(self, status, message):
         super().__init__(f"{message} (status {status})")
@@ -90,6 +99,9 @@ _SIGS = {
     "te_set_allocator": (_I, [_P, _P, _P]),
     "te_evolve": (_I, [_P, _P, _P, _D, _D, _I, ctypes.POINTER(te_options), ctypes.POINTER(te_result), _P]),
     "te_last_profile": (_I, [_P, ctypes.POINTER(te_profile)]),
+    "te_autotune": (_I, [_P, _I, ctypes.POINTER(te_tuning), _P]),
+    "te_get_tuning": (_I, [_P, ctypes.POINTER(te_tuning)]),
+    "te_set_tuning": (_I, [_P, ctypes.POINTER(te_tuning)]),
     "te_spmv": (_I, [_P, _P, _P, ctypes.POINTER(te_c128), _P]),
     "te_arnoldi": (_I, [_P, _P, _I, _D, _P, _PD, _PD, _PI, _P]),
     "te_tridiag_eig": (_I, [_I, _PD, _PD, _PD, _PD, _P]),
@@ -216,6 +228,23 @@ def te_evolve(H: Hamiltonian, v0, t: float, tol: float, m: int, options=None, ou
     opt = ctypes.byref(options) if options is not None else None
     _check(_lib.te_evolve(H.handle, p0, p1, float(t), float(tol), int(m), opt, ctypes.byref(res), _stream(stream)))
     return out, res
+
+
+def te_autotune(H: Hamiltonian, m: int, stream=None) -> te_tuning:
+    t = te_tuning()
+    _check(_lib.te_autotune(H.handle, int(m), ctypes.byref(t), _stream(stream)))
+    return t
+
+
+def te_get_tuning(H: Hamiltonian) -> te_tuning:
+    t = te_tuning()
+    _check(_lib.te_get_tuning(H.handle, ctypes.byref(t)))
+    return t
+
+
+def te_set_tuning(H: Hamiltonian, lanes_per_row, nnz_per_lane, rows_per_thread, update_rows_per_thread):
+    t = te_tuning(lanes_per_row, nnz_per_lane, rows_per_thread, update_rows_per_thread, 0.0)
+    _check(_lib.te_set_tuning(H.handle, ctypes.byref(t)))
 
 
 def te_last_profile(H: Hamiltonian) -> te_profile:

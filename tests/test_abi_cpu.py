@@ -42,7 +42,7 @@ def test_host_only_calls():
     assert "step" in te.te_status_string(te.TE_ERR_STEP_UNDERFLOW)
     # workspace: 40 basis columns + work vector of 2^20 complex numbers, plus small scratch
     b = te.te_workspace_bytes(1 << 20, 40)
-    assert 41 * (1 << 20) * 16 <= b <= 41 * (1 << 20) * 16 + (8 << 20)
+    assert 41 * (1 << 20) * 16 <= b <= 41 * (1 << 20) * 16 + (16 << 20)
     assert te.te_workspace_bytes(0, 40) == 0
     assert te.te_workspace_bytes(100, 200) == te.te_workspace_bytes(100, 100)
 

@@ -331,3 +331,42 @@ def test_error_paths():
         # the handle still works after errors
         v, res = te.te_evolve(h, x, 2.0, 1e-8, 20)
         assert res.err_bound <= 1e-8
+
+
+# ------------------------------------------------------------------- autotuned kernel shapes
+SHAPES = [(4, 1, 1, 1), (4, 4, 1, 1), (8, 2, 1, 1), (4, 1, 2, 2), (4, 4, 2, 2), (8, 2, 2, 2), (8, 2, 1, 2)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_every_kernel_shape_matches_oracle(shape):
+    announce(f"shape {shape}")
+    te = lib()
+    for H, v0, t, tol, m in [(*W.xxz_chain(11, seed=3), 6.0, 1e-8, 30),
+                              (random_hermitian_csr(1537, 0.006, 11), None, 3.0, 1e-9, 24)]:
+        if v0 is None:
+            v0 = W.random_state(np.random.default_rng(11), H.dim)
+        with hamiltonian(H) as h:
+            te.te_set_tuning(h, *shape)
+            got = te.te_get_tuning(h)
+            assert (got.lanes_per_row, got.nnz_per_lane, got.rows_per_thread, got.update_rows_per_thread) == shape
+            v, res = te.te_evolve(h, to_dev(v0), t, tol, m)
+            v = to_host(v)
+        ro = O.evolve(H, v0, t, tol, m)
+        assert np.linalg.norm(v - ro.v) <= 2 * tol + 1e-12
+        assert abs(res.steps - ro.steps) <= 1
+
+
+def test_autotune_picks_a_supported_shape():
+    announce("autotune")
+    te = lib()
+    wl = W.workload("xxz_L12")
+    with hamiltonian(wl.H) as h:
+        t = te.te_autotune(h, 40)
+        assert (t.lanes_per_row, t.nnz_per_lane) in [(4, 1), (4, 4), (8, 2)]
+        assert t.rows_per_thread in (1, 2) and t.project_us > 0
+        v, res = te.te_evolve(h, to_dev(wl.v0), wl.t, wl.tol, wl.m)
+    ro = O.evolve(wl.H, wl.v0, wl.t, wl.tol, wl.m)
+    assert np.linalg.norm(to_host(v) - ro.v) <= 2 * wl.tol + 1e-12
+    with pytest.raises(te.TEError):
+        with hamiltonian(wl.H) as h:
+            te.te_set_tuning(h, 8, 4, 1, 1)
