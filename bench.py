@@ -36,6 +36,21 @@ def percentile(xs, q):
     return float(np.percentile(np.asarray(xs), q))
 
 
+def measured_traffic(kernel_source):
+    """HBM bytes per projection launch from the committed counter runs, or None when the kernel
+    source changed since they were taken (profiles/xxz_L20_hbm_traffic.json)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "xxz_L20_hbm_traffic.json")
+    try:
+        rec = json.load(open(path))
+        src = hashlib.sha256(open(kernel_source, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256_arnoldi_hip") != src:
+        return None
+    return rec
+
+
 def cpu_baseline(wl, gpu_restarts, n_restarts):
     """The CPU oracle, as it stands, on a bounded sample: its first n_restarts restarts of the same
     workload, extrapolated to a whole solve with the restart count of the GPU solve."""
@@ -122,6 +137,7 @@ def main():
     graph_elapsed = time.perf_counter() - g0
 
     kernel_gbs = {k: (v["bytes"] / v["seconds"] / 1e9 if v["seconds"] > 0 else None) for k, v in totals.items()}
+    traffic = measured_traffic(os.path.join(ROOT, "paper_2205_15346_amd", "csrc", "arnoldi.hip"))
     dominant = max(totals, key=lambda k: totals[k]["seconds"])
     dom = totals[dominant]
     achieved = dom["bytes"] / dom["seconds"] / 1e9
@@ -156,7 +172,9 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic["project_bytes_per_launch"] if (traffic and dominant == "project") else None,
+            "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "algorithmic_bytes_per_launch": dom["bytes"] / max(dom["launches"], 1),
         },
         "cpu_baseline": {k: v for k, v in cpu.items() if k != "seconds_per_solve"} if cpu else None,
         "hbm_gbs_algorithmic_all_kernels": alg_bytes / kernel_seconds / 1e9,
