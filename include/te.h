@@ -48,7 +48,8 @@ enum {
     TE_ERR_DEVICE = 6,         /* a HIP runtime error; te_last_error() holds its text */
     TE_ERR_STEP_UNDERFLOW = 7, /* the step search halved max_halvings times without success */
     TE_ERR_NONFINITE = 8,      /* NaN/Inf met in v0 or during the iteration */
-    TE_ERR_CAPACITY = 9        /* batch / engine capacity or memory budget exceeded */
+    TE_ERR_CAPACITY = 9,       /* batch / engine capacity or memory budget exceeded */
+    TE_ERR_TIMEOUT = 10        /* te_engine_wait: the jobs waited for are not done yet */
 };
 
 /* warning bits of te_result.warnings (they never change the status) */
@@ -230,6 +231,115 @@ te_status te_step_search(int32_t k, const double* alpha, const double* beta, dou
                          double tol_rate, double t_rem, int32_t first, double tau_prev,
                          int32_t breakdown, const te_options* opt, double* tau, double* err,
                          te_c128* omega, uint32_t* warnings, void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Batched and served evolution.  An engine advances many jobs, each one te_evolve problem
+ * (H, v0, t, tol) with the engine's m and options, together in rounds: one round runs one
+ * restart of Alg. 1 (Krylov build, step-size choice, recombination) for every resident job,
+ * with batched kernels whose workgroups are (job, row tile) items of all jobs at once.  Jobs
+ * sharing one Hamiltonian handle stream its CSR once per Krylov iteration for up to 8 vectors
+ * (a multi-vector sparse product).  A round is one hipGraph launch; all step decisions stay on
+ * the device, the host only keeps rounds queued and reads completion records written by the
+ * device into mapped host memory.
+ *
+ * Scheduling points are round boundaries.  There, completed jobs leave (their workspace is
+ * returned to the pool) and queued jobs are admitted in submission order while a slot is free
+ * and te_job_footprint(dim, m) bytes fit in the pool (first fit).  H, the basis and the job
+ * state stay resident across restarts.  A job's arithmetic does not depend on the other jobs
+ * of a round: with one kernel shape its result is bitwise the same alone and in any mix.
+ *
+ * Job buffers: v0 and v_out are device pointers of dim complex owned by the caller; v0 must
+ * hold its data when te_engine_submit is called and stay unchanged until the job is admitted,
+ * v_out must stay valid until the job is done (it is complete once te_engine_poll reports
+ * TE_JOB_DONE); v_out may equal v0.  The Hamiltonian handle must outlive its jobs; a handle in
+ * use by an engine must not be passed to te_evolve concurrently (it is only read, but
+ * te_hamiltonian_destroy would free it). */
+typedef struct te_engine_s* te_engine;
+typedef int64_t te_job;
+
+#define TE_ENGINE_THREADED 1u /* a worker thread schedules rounds; otherwise rounds advance
+                                 inside te_engine_wait / te_batch_launch */
+#define TE_ENGINE_PROFILE 2u  /* no graphs, no lookahead: an event around every kernel class;
+                                 te_engine_stats.prof accumulates times and algorithmic bytes */
+
+typedef struct {
+    int32_t m;                      /* Krylov dimension, 2..TE_MAX_KRYLOV (clamped per job to dim) */
+    int32_t max_jobs;               /* resident jobs at most, 1..16384 */
+    uint64_t hbm_budget;            /* bytes of device memory for job workspaces, allocated once */
+    int32_t lanes_per_row;          /* projection shape: 4 or 8 lanes per row; 0 = autotune */
+    int32_t nnz_per_lane;           /* 1 or 4 with 4 lanes, 2 with 8 lanes */
+    int32_t update_rows_per_thread; /* 1 or 2; 0 = 2 if a resident dim >= 2^19, else 1 */
+    uint32_t flags;                 /* TE_ENGINE_* */
+    te_options opt;                 /* step-size / quadrature options (opt.flags must be 0) */
+} te_engine_config;
+
+enum { TE_JOB_QUEUED = 0, TE_JOB_RUNNING = 1, TE_JOB_DONE = 2, TE_JOB_FAILED = 3 };
+
+typedef struct {
+    int32_t state;      /* TE_JOB_* */
+    te_status status;   /* TE_OK, or why the job failed */
+    int32_t rounds;     /* rounds the job was resident for */
+    int32_t steps;      /* restarts completed so far */
+    double t_now;       /* time reached so far */
+    double submitted, admitted, finished; /* host monotonic clock (seconds; 0 = not yet) */
+} te_job_info;
+
+typedef struct {
+    int64_t rounds;       /* rounds completed */
+    int64_t plans;        /* round graphs built (one per change of the resident set) */
+    int64_t jobs_submitted, jobs_done, jobs_failed, jobs_queued, jobs_running;
+    uint64_t pool_bytes, pool_used, pool_peak;
+    double busy_seconds;  /* wall time with at least one job resident */
+    te_tuning tuning;     /* shape in use (project_us: autotuned time of one projection round) */
+    te_profile prof;      /* TE_ENGINE_PROFILE only: per kernel class, summed over rounds */
+} te_engine_stats;
+
+/* Device bytes one job of dimension dim takes from the pool (basis m x dim, product vector,
+ * reduction partials); 0 for invalid arguments.  Host-only. */
+uint64_t te_job_footprint(int64_t dim, int32_t m);
+
+/* Fills the defaults: m=40, max_jobs=1024, hbm_budget=0 (must be set), autotuned shape,
+ * threaded, te_default_options. */
+void te_engine_default_config(te_engine_config* cfg);
+
+/* Allocates the pool (hbm_budget bytes) and the job slots on the current device.  stream:
+ * the engine's work stream (NULL: the engine creates a non-blocking stream of its own).
+ * TE_ENGINE_THREADED starts the scheduler thread. */
+te_status te_engine_create(te_engine* out, const te_engine_config* cfg, void* stream);
+
+/* Queues one job; returns its id (ids increase from 0).  Thread-safe, never blocks on the
+ * device.  TE_ERR_CAPACITY if the job's footprint exceeds the whole pool (it could never be
+ * admitted); TE_ERR_INVALID_ARG for the te_evolve argument rules.  t == 0 completes at once
+ * (v_out = v0). */
+te_status te_engine_submit(te_engine e, te_hamiltonian h, const te_c128* v0, te_c128* v_out,
+                           double t, double tol, te_job* id);
+
+/* State of a job; res (may be NULL) is filled once the job is done or failed. */
+te_status te_engine_poll(te_engine e, te_job id, te_job_info* info, te_result* res);
+
+/* Waits until job id (or every job submitted so far, for id = -1) is done or failed, or the
+ * timeout (seconds; < 0 = none) expires: TE_ERR_TIMEOUT.  Without TE_ENGINE_THREADED the
+ * rounds run inside this call.  Returns TE_ERR_DEVICE if the engine failed. */
+te_status te_engine_wait(te_engine e, te_job id, double timeout_s);
+
+te_status te_engine_get_stats(te_engine e, te_engine_stats* out);
+
+/* Stops the scheduler, waits for the device, frees the pool.  Jobs not done are dropped. */
+te_status te_engine_destroy(te_engine e);
+
+/* Batch: a fixed set of jobs run to completion by an engine without a scheduler thread.
+ * te_batch_add appends n jobs on one H (v0[i], v_out[i]: host arrays of n device pointers)
+ * and returns the index of the first; te_batch_launch runs every job (hbm_budget 0: the sum
+ * of the footprints, so all jobs are resident from the first round) and returns once all are
+ * done; te_batch_result gives a job's result and status.  cfg: as for te_engine_create
+ * (max_jobs 0 = all jobs, hbm_budget ignored; TE_ENGINE_THREADED ignored). */
+typedef struct te_batch_s* te_batch;
+te_status te_batch_create(te_batch* out, const te_engine_config* cfg, void* stream);
+te_status te_batch_add(te_batch b, te_hamiltonian h, int32_t n, const te_c128* const* v0,
+                       te_c128* const* v_out, double t, double tol, int32_t* first);
+te_status te_batch_launch(te_batch b, uint64_t hbm_budget, te_engine_stats* stats);
+te_status te_batch_result(te_batch b, int32_t i, te_result* res, te_status* status);
+te_status te_batch_destroy(te_batch b);
 
 #ifdef __cplusplus
 }

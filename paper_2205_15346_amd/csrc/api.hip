@@ -42,6 +42,12 @@ te_status fail(te_status s, const std::string& msg) {
                         std::string(#call) + ": " + hipGetErrorString(e_));                            \
     } while (0)
 
+}  // namespace
+
+namespace te {
+
+te_status set_error(te_status s, const std::string& msg) { return fail(s, msg); }
+
 void* dev_alloc(size_t bytes) {
     if (bytes == 0) bytes = 1;
     if (g_alloc) return g_alloc(bytes, g_alloc_ctx);
@@ -58,7 +64,7 @@ void dev_free(void* p) {
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-}  // namespace
+}  // namespace te
 
 // ------------------------------------------------------------------------- workspace
 namespace te {
@@ -118,24 +124,12 @@ struct Workspace {
 
 }  // namespace te
 
-struct te_hamiltonian_s {
-    Csr csr{};
-    int* row_ptr = nullptr;
-    int* col = nullptr;
-    double2* val = nullptr;
-    double norm1 = 0.0;
-    std::mutex mu;
-    Workspace* ws = nullptr;
-    te_profile prof{};
-    bool tuned = false;        // tuning measured or set explicitly
-    te_tuning tuning{4, 4, 1, 1, 0.0};
-    ~te_hamiltonian_s() {
-        delete ws;
-        dev_free(row_ptr);
-        dev_free(col);
-        dev_free(val);
-    }
-};
+te_hamiltonian_s::~te_hamiltonian_s() {
+    delete ws;
+    dev_free(row_ptr);
+    dev_free(col);
+    dev_free(val);
+}
 
 namespace {
 
@@ -286,23 +280,6 @@ te_status ensure_graph(te_hamiltonian h, Workspace* w) {
     return TE_OK;
 }
 
-Problem make_problem(te_hamiltonian h, const te_options& o, double t, double tol, int m) {
-    Problem p{};
-    p.t = t;
-    p.tol_rate = tol / t;
-    p.numerr_per_step = (double)h->csr.dim * h->norm1 * std::ldexp(1.0, -52);
-    p.t_init = o.t_init;
-    p.shrink = o.shrink;
-    p.quad_rel_tol = o.quad_rel_tol;
-    p.m = m;
-    p.dim = h->csr.dim;
-    p.n_substeps = o.n_substeps;
-    p.quad_max_level = o.quad_max_level;
-    p.quad_min_level = o.quad_min_level;
-    p.max_halvings = o.max_halvings;
-    return p;
-}
-
 // re-point a workspace at a new tiling (the partial buffers fit every tiling)
 te_status retile(te_hamiltonian h, Workspace* w, const Tiling& t) {
     w->tl = t;
@@ -431,6 +408,27 @@ te_status get_workspace(te_hamiltonian h, int m, Workspace** out) {
     return TE_OK;
 }
 
+}  // namespace
+
+namespace te {
+
+Problem make_problem(const te_hamiltonian_s* h, const te_options& o, double t, double tol, int m) {
+    Problem p{};
+    p.t = t;
+    p.tol_rate = tol / t;
+    p.numerr_per_step = (double)h->csr.dim * h->norm1 * std::ldexp(1.0, -52);
+    p.t_init = o.t_init;
+    p.shrink = o.shrink;
+    p.quad_rel_tol = o.quad_rel_tol;
+    p.m = m;
+    p.dim = h->csr.dim;
+    p.n_substeps = o.n_substeps;
+    p.quad_max_level = o.quad_max_level;
+    p.quad_min_level = o.quad_min_level;
+    p.max_halvings = o.max_halvings;
+    return p;
+}
+
 te_status check_options(const te_options& o) {
     if (o.n_substeps < 1 || !(o.t_init > 0.0) || !std::isfinite(o.t_init) || !(o.shrink > 0.0) || !(o.shrink <= 1.0) ||
         !(o.quad_rel_tol > 0.0) || o.quad_max_level < 0 || o.quad_max_level > 20 || o.quad_min_level < 0 ||
@@ -439,7 +437,7 @@ te_status check_options(const te_options& o) {
     return TE_OK;
 }
 
-}  // namespace
+}  // namespace te
 
 // ============================================================================== C ABI
 extern "C" {

@@ -50,8 +50,7 @@ Tiling default_tiling(int dim) {
 }
 
 // ------------------------------------------------------------------- setup / copy
-__global__ void k_setup(DevState* __restrict__ st, Problem prob) {
-    if (threadIdx.x != 0) return;
+__device__ __forceinline__ void setup_state(DevState* __restrict__ st, const Problem& prob) {
     st->p = prob;
     st->beta0 = 0.0;
     st->t_now = 0.0;
@@ -70,9 +69,14 @@ __global__ void k_setup(DevState* __restrict__ st, Problem prob) {
     st->breakdown = 0;
     st->k_comb = 0;
     st->norm_init = 1;
+    st->counted = 0;
     st->h = 0.0;
     st->ys = 1.0;
     st->s[0] = 1.0;
+}
+
+__global__ void k_setup(DevState* __restrict__ st, Problem prob) {
+    if (threadIdx.x == 0) setup_state(st, prob);
 }
 
 __global__ __launch_bounds__(kBlock) void k_copy(const double2* __restrict__ src, double2* __restrict__ dst, int dim) {
@@ -105,16 +109,16 @@ __device__ __forceinline__ double halving_reduce32(double (&a)[32], int lane) {
 }
 
 template <int RPT, int G, int U>
-__global__ __launch_bounds__(kBlock) void k_project(const int* __restrict__ rp, const int* __restrict__ ci,
-                                                     const double2* __restrict__ val, const double2* __restrict__ V,
-                                                     int64_t ld, int dim, int j, double2* __restrict__ y,
-                                                     const DevState* __restrict__ st, RedBuf rb) {
+__device__ __forceinline__ void project_body(const int* __restrict__ rp, const int* __restrict__ ci,
+                                             const double2* __restrict__ val, const double2* __restrict__ V,
+                                             int64_t ld, int dim, int j, double2* __restrict__ y,
+                                             const DevState* __restrict__ st, const RedBuf& rb, int tile) {
     constexpr int R = kBlock * RPT;
     __shared__ double2 ytile[R];
     __shared__ double2 wpart[kWaves][kMaxVals];
     if (st->done || j >= st->k_limit) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int r0 = blockIdx.x * R;
+    const int r0 = tile * R;
     const int r1 = min(r0 + R, dim);
     const double2* __restrict__ x = V + (int64_t)j * ld;
 
@@ -206,21 +210,174 @@ __global__ __launch_bounds__(kBlock) void k_project(const int* __restrict__ rp, 
     for (int v = tid; v < nv; v += kBlock) {
         double2 s = make_double2(0.0, 0.0);
         for (int w = 0; w < kWaves; ++w) s = cadd(s, wpart[w][v]);
-        rb.part[(size_t)v * rb.n_tiles + blockIdx.x] = s;
+        rb.part[(size_t)v * rb.n_tiles + tile] = s;
+    }
+}
+
+template <int RPT, int G, int U>
+__global__ __launch_bounds__(kBlock) void k_project(const int* __restrict__ rp, const int* __restrict__ ci,
+                                                     const double2* __restrict__ val, const double2* __restrict__ V,
+                                                     int64_t ld, int dim, int j, double2* __restrict__ y,
+                                                     const DevState* __restrict__ st, RedBuf rb) {
+    project_body<RPT, G, U>(rp, ci, val, V, ld, dim, j, y, st, rb, blockIdx.x);
+}
+
+// Batched projection: one workgroup per (group, tile).  The jobs of a group share H, so the
+// sparse product streams each (column, value) pair once and applies it to every vector of the
+// group (a multi-vector product, NV >= group size); the projections then run per vector.
+// Tiles are kBlock rows (one row per thread in the dense part).
+template <int G, int U, int NV>
+__global__ __launch_bounds__(kBlock) void k_gproject(const JobView* __restrict__ jobs,
+                                                      const GroupView* __restrict__ groups,
+                                                      const int2* __restrict__ items, int j) {
+    __shared__ double2 ytile[NV][kBlock];
+    __shared__ double2 wpart[kWaves][kMaxVals];
+    const int2 it = items[blockIdx.x];
+    const GroupView& gv = groups[it.x];
+    const int tile = it.y;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int dim = gv.dim;
+    const int r0 = tile * kBlock;
+    const int r1 = min(r0 + kBlock, dim);
+
+    unsigned mask = 0;
+    const double2* xs[NV];
+    double2* ys[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        xs[v] = nullptr;
+        ys[v] = nullptr;
+        if (v < gv.nv) {
+            const JobView& J = jobs[gv.job[v]];
+            const DevState* st = J.st;
+            if (!st->done && j < st->k_limit) {
+                mask |= 1u << v;
+                xs[v] = J.V + (int64_t)j * J.ld;
+                ys[v] = J.y;
+            }
+        }
+    }
+    if (mask == 0) return;
+    const int* __restrict__ rp = gv.rp;
+    const int* __restrict__ ci = gv.ci;
+    const double2* __restrict__ val = gv.val;
+
+    // y_v = H V_v[:, j] for every live vector: G lanes per row, U nonzeros in flight each
+    {
+        const int lg = tid % G, grp = tid / G;
+        for (int r = r0 + grp; r < r1; r += kBlock / G) {
+            double2 acc[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) acc[v] = make_double2(0.0, 0.0);
+            const int kb = rp[r], ke = rp[r + 1];
+            for (int k0 = kb + lg; k0 < ke; k0 += G * U) {
+                double2 vv[U];
+                int cc[U];
+#pragma unroll
+                for (int q = 0; q < U; ++q) {
+                    const int k = k0 + q * G;
+                    if (k < ke) {
+                        vv[q] = val[k];
+                        cc[q] = ci[k];
+                    } else {
+                        vv[q] = make_double2(0.0, 0.0);
+                        cc[q] = -1;
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < U; ++q) {
+                    if (cc[q] < 0) continue;
+#pragma unroll
+                    for (int v = 0; v < NV; ++v)
+                        if (mask & (1u << v)) acc[v] = cfma(vv[q], xs[v][cc[q]], acc[v]);
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+#pragma unroll
+                for (int o = G / 2; o > 0; o >>= 1) {
+                    acc[v].x += __shfl_xor(acc[v].x, o);
+                    acc[v].y += __shfl_xor(acc[v].y, o);
+                }
+                if (lg == 0 && (mask & (1u << v))) {
+                    ys[v][r] = acc[v];
+                    ytile[v][r - r0] = acc[v];
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // projections, one vector at a time: c'_i = V_i^H y and g_i = V_i^H V_j on this tile
+    const int r = r0 + tid;
+#pragma unroll 1
+    for (int v = 0; v < NV; ++v) {
+        if (!(mask & (1u << v))) continue;
+        const JobView& J = jobs[gv.job[v]];
+        const double2* __restrict__ V = J.V;
+        const int64_t ld = J.ld;
+        double2 yq = make_double2(0.0, 0.0), xq = make_double2(0.0, 0.0);
+        if (r < r1) {
+            yq = ytile[v][tid];
+            xq = V[(int64_t)j * ld + r];
+        }
+        for (int i0 = 0; i0 <= j; i0 += 8) {
+            double a[32];
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                double2 cy = make_double2(0.0, 0.0), cx = make_double2(0.0, 0.0);
+                const int i = i0 + b;
+                if (i <= j && r < r1) {
+                    const double2 w = V[(int64_t)i * ld + r];
+                    cy = cfma_conj(w, yq, cy);
+                    cx = cfma_conj(w, xq, cx);
+                }
+                a[4 * b] = cy.x;
+                a[4 * b + 1] = cy.y;
+                a[4 * b + 2] = cx.x;
+                a[4 * b + 3] = cx.y;
+            }
+            const double sum = halving_reduce32(a, lane);
+            if ((lane & 1) == 0) {
+                const int q = lane >> 1;
+                const int i = i0 + (q >> 2);
+                if (i <= j) {
+                    double* dst = (double*)&wpart[wave][2 * i + ((q >> 1) & 1)];
+                    dst[q & 1] = sum;
+                }
+            }
+        }
+        __syncthreads();
+        const int nvals = 2 * (j + 1);
+        for (int q = tid; q < nvals; q += kBlock) {
+            double2 sum = make_double2(0.0, 0.0);
+            for (int w = 0; w < kWaves; ++w) sum = cadd(sum, wpart[w][q]);
+            J.rb.part[(size_t)q * J.rb.n_tiles + tile] = sum;
+        }
+        __syncthreads();
     }
 }
 
 // ---------------------------------------------------- fold of the projection partials
-// Block v folds value v over all tiles in a fixed order.
-__global__ __launch_bounds__(kBlock) void k_fold(const DevState* __restrict__ st, RedBuf rb, int j) {
+// Folds value v of iteration j over all tiles in a fixed order (whole block).
+__device__ __forceinline__ void fold_value(const DevState* __restrict__ st, const RedBuf& rb, int j, int v) {
     __shared__ double lds[kWaves];
     if (st->done || j >= st->k_limit) return;
-    const int v = blockIdx.x;
     double2 acc = make_double2(0.0, 0.0);
     for (int t = threadIdx.x; t < rb.n_tiles; t += kBlock) acc = cadd(acc, rb.part[(size_t)v * rb.n_tiles + t]);
     const double sx = block_sum(acc.x, lds);
     const double sy = block_sum(acc.y, lds);
     if (threadIdx.x == 0) rb.red[v] = make_double2(sx, sy);
+}
+
+__global__ __launch_bounds__(kBlock) void k_fold(const DevState* __restrict__ st, RedBuf rb, int j) {
+    fold_value(st, rb, j, blockIdx.x);
+}
+
+// batched: grid (2(j+1), jobs)
+__global__ __launch_bounds__(kBlock) void k_bfold(const JobView* __restrict__ jobs, int j) {
+    const JobView& J = jobs[blockIdx.y];
+    fold_value(J.st, J.rb, j, blockIdx.x);
 }
 
 // ----------------------------------------------------------------- update: new column
@@ -230,16 +387,16 @@ __global__ __launch_bounds__(kBlock) void k_fold(const DevState* __restrict__ st
 //   c_i = c'_i - E_{i,j} c'_j - E_{i,j-1} c'_{j-1}, E = G - I, column j-1 of G from iteration j-1.
 // Body: V[:, j+1] = s_j y - sum_i c_i s_i V[:, i]; the last residual only yields its norm.
 template <int RPT>
-__global__ __launch_bounds__(kBlock) void k_update(double2* __restrict__ V, int64_t ld, int dim, int j,
-                                                    const double2* __restrict__ y, DevState* __restrict__ st,
-                                                    RedBuf rb) {
+__device__ __forceinline__ void update_body(double2* __restrict__ V, int64_t ld, int dim, int j,
+                                            const double2* __restrict__ y, DevState* __restrict__ st,
+                                            const RedBuf& rb, int tile) {
     __shared__ double lds[kWaves];
     __shared__ double2 cp[kMaxM + 1], g[kMaxM + 1], cs[kMaxM + 1];
     __shared__ double sj_sh;
     __shared__ int stop_sh;
     if (st->done || j >= st->k_limit) return;
     const int tid = threadIdx.x;
-    const bool rec = blockIdx.x == 0;
+    const bool rec = tile == 0;
     if (tid == 0) {
         int stop = 0;
         double sj;
@@ -328,7 +485,7 @@ __global__ __launch_bounds__(kBlock) void k_update(double2* __restrict__ V, int6
     }
     __syncthreads();
 
-    const int r0 = blockIdx.x * (kBlock * RPT);
+    const int r0 = tile * (kBlock * RPT);
     const bool last = (j + 1) == st->p.m;
     double2 p[RPT];
 #pragma unroll
@@ -360,8 +517,24 @@ __global__ __launch_bounds__(kBlock) void k_update(double2* __restrict__ V, int6
             acc = fma(p[q].y, p[q].y, acc);
         }
         const double s = block_sum(acc, lds);
-        if (tid == 0) rb.npart[blockIdx.x] = s;
+        if (tid == 0) rb.npart[tile] = s;
     }
+}
+
+template <int RPT>
+__global__ __launch_bounds__(kBlock) void k_update(double2* __restrict__ V, int64_t ld, int dim, int j,
+                                                    const double2* __restrict__ y, DevState* __restrict__ st,
+                                                    RedBuf rb) {
+    update_body<RPT>(V, ld, dim, j, y, st, rb, blockIdx.x);
+}
+
+template <int RPT>
+__global__ __launch_bounds__(kBlock) void k_bupdate(const JobView* __restrict__ jobs, const int2* __restrict__ items,
+                                                     int j) {
+    const int2 it = items[blockIdx.x];
+    if (it.x < 0) return;
+    const JobView& J = jobs[it.x];
+    update_body<RPT>(J.V, J.ld, J.dim, j, J.y, J.st, J.rb, it.y);
 }
 
 __global__ __launch_bounds__(kBlock) void k_last_norm(DevState* st, RedBuf rb) {
@@ -371,11 +544,11 @@ __global__ __launch_bounds__(kBlock) void k_last_norm(DevState* st, RedBuf rb) {
 
 // ------------------------------------------------------------- recombination w = V omega
 template <int RPT>
-__global__ __launch_bounds__(kBlock) void k_combine(double2* __restrict__ V, int64_t ld, int dim,
-                                                     const DevState* __restrict__ st) {
+__device__ __forceinline__ void combine_body(double2* __restrict__ V, int64_t ld, int dim,
+                                             const DevState* __restrict__ st, int tile) {
     if (!st->do_combine) return;
     const int k = st->k_comb;
-    const int r0 = blockIdx.x * (kBlock * RPT);
+    const int r0 = tile * (kBlock * RPT);
     double2 w[RPT];
 #pragma unroll
     for (int q = 0; q < RPT; ++q) w[q] = make_double2(0.0, 0.0);
@@ -392,6 +565,94 @@ __global__ __launch_bounds__(kBlock) void k_combine(double2* __restrict__ V, int
     for (int q = 0; q < RPT; ++q) {
         const int r = r0 + threadIdx.x + q * kBlock;
         if (r < dim) V[r] = w[q];
+    }
+}
+
+template <int RPT>
+__global__ __launch_bounds__(kBlock) void k_combine(double2* __restrict__ V, int64_t ld, int dim,
+                                                     const DevState* __restrict__ st) {
+    combine_body<RPT>(V, ld, dim, st, blockIdx.x);
+}
+
+template <int RPT>
+__global__ __launch_bounds__(kBlock) void k_bcombine(const JobView* __restrict__ jobs, const int2* __restrict__ items) {
+    const int2 it = items[blockIdx.x];
+    if (it.x < 0) return;
+    const JobView& J = jobs[it.x];
+    combine_body<RPT>(J.V, J.ld, J.dim, J.st, it.y);
+}
+
+// ------------------------------------------------------- batched setup, copy, output
+__global__ void k_bsetup(const JobView* __restrict__ jobs, const Problem* __restrict__ probs, int n) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n) setup_state(jobs[r].st, probs[r]);
+}
+
+// rows of one update tile (rpt rows per thread): V[:, 0] = v0 or out = beta0 s_0 V[:, 0]
+__global__ __launch_bounds__(kBlock) void k_bcopy_in(const JobView* __restrict__ jobs, const int2* __restrict__ items,
+                                                      int rpt) {
+    const int2 it = items[blockIdx.x];
+    if (it.x < 0) return;
+    const JobView& J = jobs[it.x];
+    for (int q = 0; q < rpt; ++q) {
+        const int r = it.y * kBlock * rpt + q * kBlock + threadIdx.x;
+        if (r < J.dim) J.V[r] = J.v0[r];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_bcopy_out(const JobView* __restrict__ jobs, const int2* __restrict__ items,
+                                                       int rpt) {
+    const int2 it = items[blockIdx.x];
+    if (it.x < 0) return;
+    const JobView& J = jobs[it.x];
+    const DevState* st = J.st;
+    if (!st->done || st->counted) return;  // only jobs that completed in this round
+    const double b = (st->beta0 == 0.0) ? 0.0 : st->beta0 * st->s[0];
+    for (int q = 0; q < rpt; ++q) {
+        const int r = it.y * kBlock * rpt + q * kBlock + threadIdx.x;
+        if (r < J.dim) J.out[r] = cscale(J.V[r], b);
+    }
+}
+
+// End of a batched round (one workgroup): write the round record of every job that has not
+// yet reported its completion into bank (round & 1) of the host-mapped records, mark the jobs
+// that completed in this round as reported, and advance the round counter.
+__global__ __launch_bounds__(kBlock) void k_bflag(const JobView* __restrict__ jobs, int n, int* __restrict__ rounds,
+                                                   SlotOut* __restrict__ slots, int max_slots,
+                                                   RoundOut* __restrict__ ro) {
+    __shared__ double lds[kWaves];
+    const int round = *rounds + 1;
+    SlotOut* bank = slots + (size_t)(round & 1) * max_slots;
+    double live = 0.0;
+    for (int i = threadIdx.x; i < n; i += kBlock) {
+        const JobView& J = jobs[i];
+        DevState* st = J.st;
+        if (st->counted) continue;
+        SlotOut o;
+        o.id = J.id;
+        o.done = st->done;
+        o.status = st->status;
+        o.steps = st->steps;
+        o.matvecs = st->matvecs;
+        o.breakdown_dim = st->breakdown_dim;
+        o.warnings = st->warnings;
+        o.last_k = st->k_comb;
+        o.round = round;
+        o.beta0 = st->beta0;
+        o.err_acc = st->err_acc;
+        o.num_acc = st->num_acc;
+        o.t_now = st->t_now;
+        bank[J.slot] = o;
+        if (st->done) st->counted = 1;
+        else live += 1.0;
+    }
+    const double total = block_sum(live, lds);
+    __threadfence_system();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        *rounds = round;
+        __hip_atomic_store(&ro->active, (int)total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&ro->rounds, round, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 
@@ -528,6 +789,70 @@ static hipError_t by_rpt(int rpt, F&& f) {
 }
 
 static int grid_for(int dim) { return (int)std::min<int64_t>(((int64_t)dim + kBlock - 1) / kBlock, 4096); }
+
+// ----------------------------------------------------------------- batched launchers
+bool gproject_supported(int g, int u) { return (g == 4 && (u == 1 || u == 4)) || (g == 8 && u == 2); }
+
+template <int G, int U>
+static void gproject_nv(int nv_class, dim3 grid, hipStream_t s, const JobView* jobs, const GroupView* groups,
+                        const int2* items, int j) {
+    switch (nv_class) {
+        case 1: k_gproject<G, U, 1><<<grid, kBlock, 0, s>>>(jobs, groups, items, j); break;
+        case 2: k_gproject<G, U, 2><<<grid, kBlock, 0, s>>>(jobs, groups, items, j); break;
+        case 4: k_gproject<G, U, 4><<<grid, kBlock, 0, s>>>(jobs, groups, items, j); break;
+        default: k_gproject<G, U, 8><<<grid, kBlock, 0, s>>>(jobs, groups, items, j); break;
+    }
+}
+
+hipError_t launch_gproject(int g, int u, int nv_class, const JobView* jobs, const GroupView* groups,
+                           const int2* items, int n_items, int j, hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    const dim3 grid(n_items);
+    if (g == 8) gproject_nv<8, 2>(nv_class, grid, s, jobs, groups, items, j);
+    else if (u == 1) gproject_nv<4, 1>(nv_class, grid, s, jobs, groups, items, j);
+    else gproject_nv<4, 4>(nv_class, grid, s, jobs, groups, items, j);
+    return hipGetLastError();
+}
+
+hipError_t launch_bfold(const JobView* jobs, int n_jobs, int j, hipStream_t s) {
+    if (n_jobs <= 0) return hipSuccess;
+    k_bfold<<<dim3(2 * (j + 1), n_jobs), kBlock, 0, s>>>(jobs, j);
+    return hipGetLastError();
+}
+
+hipError_t launch_bupdate(int rpt, const JobView* jobs, const int2* items, int n_items, int j, hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    return by_rpt(rpt, [&](auto r) { k_bupdate<decltype(r)::value><<<n_items, kBlock, 0, s>>>(jobs, items, j); });
+}
+
+hipError_t launch_bcombine(int rpt, const JobView* jobs, const int2* items, int n_items, hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    return by_rpt(rpt, [&](auto r) { k_bcombine<decltype(r)::value><<<n_items, kBlock, 0, s>>>(jobs, items); });
+}
+
+hipError_t launch_bsetup(const JobView* jobs, const Problem* probs, int n_jobs, hipStream_t s) {
+    if (n_jobs <= 0) return hipSuccess;
+    k_bsetup<<<(n_jobs + 63) / 64, 64, 0, s>>>(jobs, probs, n_jobs);
+    return hipGetLastError();
+}
+
+hipError_t launch_bcopy_in(int rpt, const JobView* jobs, const int2* items, int n_items, hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    k_bcopy_in<<<n_items, kBlock, 0, s>>>(jobs, items, rpt);
+    return hipGetLastError();
+}
+
+hipError_t launch_bcopy_out(int rpt, const JobView* jobs, const int2* items, int n_items, hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    k_bcopy_out<<<n_items, kBlock, 0, s>>>(jobs, items, rpt);
+    return hipGetLastError();
+}
+
+hipError_t launch_bflag(const JobView* jobs, int n_jobs, int* rounds_dev, SlotOut* slots, int max_slots,
+                        RoundOut* ro, hipStream_t s) {
+    k_bflag<<<1, kBlock, 0, s>>>(jobs, n_jobs, rounds_dev, slots, max_slots, ro);
+    return hipGetLastError();
+}
 
 hipError_t launch_setup(DevState* st, const Problem& prob, hipStream_t s) {
     k_setup<<<1, 64, 0, s>>>(st, prob);

@@ -478,6 +478,14 @@ __global__ __launch_bounds__(kBlock) void k_step(DevState* st, RedBuf rb, int* h
     step_body(st, host_flag, true);
 }
 
+// batched: one workgroup per job of the round
+__global__ __launch_bounds__(kBlock) void k_bstep(const JobView* __restrict__ jobs) {
+    __shared__ double lds[kWaves];
+    const JobView& J = jobs[blockIdx.x];
+    finish_last_norm(J.st, J.rb, lds);
+    step_body(J.st, nullptr, true);
+}
+
 // step search alone on a state prepared by the host (component entry point)
 __global__ __launch_bounds__(kBlock) void k_step_only(DevState* st) { step_body(st, nullptr, false); }
 
@@ -522,6 +530,12 @@ __global__ __launch_bounds__(kBlock) void k_integral_only(int k, const double* l
 
 hipError_t launch_step(DevState* st, const RedBuf& rb, int* host_flag, hipStream_t s) {
     hipLaunchKernelGGL(k_step, dim3(1), dim3(kBlock), 0, s, st, rb, host_flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_bstep(const JobView* jobs, int n_jobs, hipStream_t s) {
+    if (n_jobs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bstep, dim3(n_jobs), dim3(kBlock), 0, s, jobs);
     return hipGetLastError();
 }
 

@@ -4,6 +4,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+#include <string>
+
 #include "te.h"
 
 namespace te {
@@ -39,6 +42,8 @@ struct DevState {
     int32_t breakdown; // lucky breakdown in this build
     int32_t k_comb;    // columns the recombination uses
     int32_t norm_init; // column 0 is the raw v0: take s[0] = 1/||column 0|| at the next projection
+    int32_t counted;   // batched engine: completion already reported to the host
+    int32_t pad_;
     double h;          // residual norm h_{k+1,k}
     double ys;         // scale of the raw product y = H V[:, j] (s[j])
     double last_tau, last_err;
@@ -60,6 +65,55 @@ struct RedBuf {
     double2* red;    // [kMaxVals] folded projection values
     int n_tiles;     // tiles of the projection kernel (rows of part)
     int n_norm;      // tiles of the update kernel (entries of npart)
+};
+
+// -------------------------------------------------------------------- batched engine
+// One evolution job of a batched round: its matrix, basis, state and reduction scratch.
+struct JobView {
+    const int* rp;
+    const int* ci;
+    const double2* val;
+    double2* V;          // basis columns, leading dimension ld
+    double2* y;          // raw product H V[:, j]
+    DevState* st;
+    RedBuf rb;           // n_tiles = tiles of the grouped projection (256 rows each)
+    const double2* v0;   // caller's initial vector (read at admission)
+    double2* out;        // caller's output vector (written when the job completes)
+    int64_t ld;
+    int64_t id;          // engine job id, echoed in the completion record
+    int dim;
+    int slot;            // index of the completion record
+};
+
+constexpr int kMaxGroup = 8;  // vectors sharing one sparse-matrix stream
+
+// Jobs of one matrix whose sparse products run as one multi-vector product.
+struct GroupView {
+    const int* rp;
+    const int* ci;
+    const double2* val;
+    int dim;
+    int nv;                // jobs in the group (1..kMaxGroup)
+    int job[kMaxGroup];    // indices into the round's JobView array
+};
+
+// Per-round record of a running job, written by the device into host-mapped memory at the end
+// of every round until the round in which the job completes (done = 1).  Records alternate
+// between two banks by round parity, so the host reads the bank of a finished round while the
+// next round writes the other one.
+struct SlotOut {
+    int64_t id;
+    int32_t done, status;
+    int32_t steps, matvecs, breakdown_dim, warnings;
+    int32_t last_k, round;  // Krylov dimension of the job's last restart; round (1-based)
+    double beta0, err_acc, num_acc, t_now;
+};
+
+// Round bookkeeping written by the device into host-mapped memory.
+struct RoundOut {
+    int32_t rounds;   // rounds completed since the engine started
+    int32_t active;   // jobs of the finished round still running
+    int32_t pad_[14];
 };
 
 // -------------------------------------------------------------------- complex helpers
@@ -159,12 +213,55 @@ hipError_t launch_scale_columns(const double2* src, double2* dst, int64_t ld, in
 hipError_t launch_validate(const Csr& H, int check_hermitian, int* err, double* rowsum, hipStream_t s);
 hipError_t launch_norm1(const double* rowsum, int dim, double* out, hipStream_t s);
 
+// batched launchers: items are (group or job, tile) pairs, one workgroup each
+hipError_t launch_gproject(int g, int u, int nv_class, const JobView* jobs, const GroupView* groups,
+                           const int2* items, int n_items, int j, hipStream_t s);
+hipError_t launch_bfold(const JobView* jobs, int n_jobs, int j, hipStream_t s);
+hipError_t launch_bupdate(int rpt, const JobView* jobs, const int2* items, int n_items, int j, hipStream_t s);
+hipError_t launch_bstep(const JobView* jobs, int n_jobs, hipStream_t s);
+hipError_t launch_bcombine(int rpt, const JobView* jobs, const int2* items, int n_items, hipStream_t s);
+hipError_t launch_bsetup(const JobView* jobs, const Problem* probs, int n_jobs, hipStream_t s);
+hipError_t launch_bcopy_in(int rpt, const JobView* jobs, const int2* items, int n_items, hipStream_t s);
+hipError_t launch_bcopy_out(int rpt, const JobView* jobs, const int2* items, int n_items, hipStream_t s);
+hipError_t launch_bflag(const JobView* jobs, int n_jobs, int* rounds_dev, SlotOut* slots, int max_slots,
+                        RoundOut* ro, hipStream_t s);
+bool gproject_supported(int g, int u);
+
 // component kernels (one block)
 hipError_t launch_eig_only(int k, const double* alpha, const double* beta, double* lambda, double* Q,
                            int* status, hipStream_t s);
 hipError_t launch_integral_only(int k, const double* lambda, const double* coef, double h, double a, double b,
                                 const Problem& opt, double* out, hipStream_t s);
 hipError_t launch_step_only(DevState* st, hipStream_t s);
+
+// ------------------------------------------------------------- host-side shared helpers
+te_status set_error(te_status s, const std::string& msg);  // thread-local te_last_error text
+void* dev_alloc(size_t bytes);                             // te_set_allocator hook or hipMalloc
+void dev_free(void* p);
+te_status check_options(const te_options& o);
+size_t align_up(size_t x, size_t a);
+
+}  // namespace te
+
+// A Hamiltonian handle: device CSR, its 1-norm, and the single-solve workspace and tuning.
+struct te_hamiltonian_s {
+    te::Csr csr{};
+    int* row_ptr = nullptr;
+    int* col = nullptr;
+    double2* val = nullptr;
+    double norm1 = 0.0;
+    std::mutex mu;
+    te::Workspace* ws = nullptr;
+    te_profile prof{};
+    bool tuned = false;  // tuning measured or set explicitly
+    te_tuning tuning{4, 4, 1, 1, 0.0};
+    ~te_hamiltonian_s();
+};
+
+namespace te {
+
+// Per-solve constants of Alg. 1 for one (H, t, tol, m).
+Problem make_problem(const te_hamiltonian_s* h, const te_options& o, double t, double tol, int m);
 
 // Whole block: fold the squared-norm partials of the last residual (iteration m-1) into
 // h = ||p|| and test it for a lucky breakdown.  No-op when a breakdown already set k < m.

@@ -23,6 +23,7 @@ TE_ERR_DEVICE = 6
 TE_ERR_STEP_UNDERFLOW = 7
 TE_ERR_NONFINITE = 8
 TE_ERR_CAPACITY = 9
+TE_ERR_TIMEOUT = 10
 TE_WARN_NUMERICAL = 1
 TE_WARN_QUADRATURE = 2
 TE_PTR_DEVICE = 1
@@ -70,6 +71,43 @@ class te_tuning(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+TE_ENGINE_THREADED = 1
+TE_ENGINE_PROFILE = 2
+TE_JOB_QUEUED, TE_JOB_RUNNING, TE_JOB_DONE, TE_JOB_FAILED = 0, 1, 2, 3
+JOB_STATES = ("queued", "running", "done", "failed")
+
+
+class te_engine_config(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int32), ("max_jobs", ctypes.c_int32), ("hbm_budget", ctypes.c_uint64),
+                ("lanes_per_row", ctypes.c_int32), ("nnz_per_lane", ctypes.c_int32),
+                ("update_rows_per_thread", ctypes.c_int32), ("flags", ctypes.c_uint32), ("opt", te_options)]
+
+
+class te_job_info(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("status", ctypes.c_int32), ("rounds", ctypes.c_int32),
+                ("steps", ctypes.c_int32), ("t_now", ctypes.c_double), ("submitted", ctypes.c_double),
+                ("admitted", ctypes.c_double), ("finished", ctypes.c_double)]
+
+    def as_dict(self):
+        d = {name: getattr(self, name) for name, _ in self._fields_}
+        d["state"] = JOB_STATES[self.state]
+        return d
+
+
+class te_engine_stats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int64), ("plans", ctypes.c_int64), ("jobs_submitted", ctypes.c_int64),
+                ("jobs_done", ctypes.c_int64), ("jobs_failed", ctypes.c_int64), ("jobs_queued", ctypes.c_int64),
+                ("jobs_running", ctypes.c_int64), ("pool_bytes", ctypes.c_uint64), ("pool_used", ctypes.c_uint64),
+                ("pool_peak", ctypes.c_uint64), ("busy_seconds", ctypes.c_double), ("tuning", te_tuning),
+                ("prof", te_profile)]
+
+    def as_dict(self):
+        d = {name: getattr(self, name) for name, _ in self._fields_ if name not in ("tuning", "prof")}
+        d["tuning"] = self.tuning.as_dict()
+        d["prof"] = self.prof.as_dict()
+        return d
+
+
 class TEError(RuntimeError):
     def __init__(self, status, message):
         super().__init__(f"{message} (status {status})")
@@ -108,6 +146,19 @@ _SIGS = {
     "te_error_integral": (_I, [_I, _PD, _PD, _D, _D, _D, ctypes.POINTER(te_options), _PD, _PI, _PI, _P]),
     "te_step_search": (_I, [_I, _PD, _PD, _D, _D, _D, _I, _D, _I, ctypes.POINTER(te_options), _PD, _PD,
                             ctypes.POINTER(te_c128), _PU, _P]),
+    "te_job_footprint": (ctypes.c_uint64, [_I64, _I]),
+    "te_engine_default_config": (None, [ctypes.POINTER(te_engine_config)]),
+    "te_engine_create": (_I, [ctypes.POINTER(_P), ctypes.POINTER(te_engine_config), _P]),
+    "te_engine_submit": (_I, [_P, _P, _P, _P, _D, _D, ctypes.POINTER(_I64)]),
+    "te_engine_poll": (_I, [_P, _I64, ctypes.POINTER(te_job_info), ctypes.POINTER(te_result)]),
+    "te_engine_wait": (_I, [_P, _I64, _D]),
+    "te_engine_get_stats": (_I, [_P, ctypes.POINTER(te_engine_stats)]),
+    "te_engine_destroy": (_I, [_P]),
+    "te_batch_create": (_I, [ctypes.POINTER(_P), ctypes.POINTER(te_engine_config), _P]),
+    "te_batch_add": (_I, [_P, _P, _I, ctypes.POINTER(_P), ctypes.POINTER(_P), _D, _D, _PI]),
+    "te_batch_launch": (_I, [_P, ctypes.c_uint64, ctypes.POINTER(te_engine_stats)]),
+    "te_batch_result": (_I, [_P, _I, ctypes.POINTER(te_result), _PI]),
+    "te_batch_destroy": (_I, [_P]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -318,6 +369,125 @@ def te_step_search(alpha, beta, h, tol_rate, t_rem, first, tau_prev, breakdown, 
                                om, ctypes.byref(warn), _stream(stream)))
     omega = np.array([complex(z.re, z.im) for z in om])
     return tau.value, err.value, omega, warn.value
+
+
+def te_job_footprint(dim: int, m: int) -> int:
+    return int(_lib.te_job_footprint(int(dim), int(m)))
+
+
+def te_engine_default_config(**overrides) -> te_engine_config:
+    c = te_engine_config()
+    _lib.te_engine_default_config(ctypes.byref(c))
+    for k, v in overrides.items():
+        setattr(c, k, v)
+    return c
+
+
+def _engine_config(m, max_jobs, hbm_budget, shape, update_rows_per_thread, flags, options):
+    c = te_engine_default_config()
+    c.m = int(m)
+    c.max_jobs = int(max_jobs)
+    c.hbm_budget = int(hbm_budget)
+    if shape is not None:
+        c.lanes_per_row, c.nnz_per_lane = int(shape[0]), int(shape[1])
+    c.update_rows_per_thread = int(update_rows_per_thread)
+    c.flags = int(flags)
+    if options is not None:
+        c.opt = options
+    return c
+
+
+class Engine:
+    """te_engine_*: continuous batching of evolve jobs.  Keeps the tensors of each job alive
+    until it is done; `submit` returns the job id."""
+
+    def __init__(self, hbm_budget, m=40, max_jobs=1024, shape=None, update_rows_per_thread=0, threaded=True,
+                 profile=False, options=None, stream=None):
+        flags = (TE_ENGINE_THREADED if threaded else 0) | (TE_ENGINE_PROFILE if profile else 0)
+        cfg = _engine_config(m, max_jobs, hbm_budget, shape, update_rows_per_thread, flags, options)
+        self._e = _P()
+        st = ctypes.c_void_p(0) if stream is None else _stream(stream)
+        _check(_lib.te_engine_create(ctypes.byref(self._e), ctypes.byref(cfg), st))
+        self._keep = {}
+
+    def submit(self, H: Hamiltonian, v0, t: float, tol: float, out=None) -> int:
+        import torch
+        p0 = _dev_c128(v0, "v0", H.dim)
+        if out is None:
+            out = torch.empty_like(v0)
+        p1 = _dev_c128(out, "out", H.dim)
+        jid = _I64()
+        _check(_lib.te_engine_submit(self._e, H.handle, p0, p1, float(t), float(tol), ctypes.byref(jid)))
+        self._keep[jid.value] = (H, v0, out)
+        return jid.value
+
+    def output(self, job: int):
+        return self._keep[job][2]
+
+    def poll(self, job: int):
+        info, res = te_job_info(), te_result()
+        _check(_lib.te_engine_poll(self._e, int(job), ctypes.byref(info), ctypes.byref(res)))
+        return info, res
+
+    def wait(self, job: int = -1, timeout: float = -1.0):
+        _check(_lib.te_engine_wait(self._e, int(job), float(timeout)))
+
+    def stats(self) -> te_engine_stats:
+        s = te_engine_stats()
+        _check(_lib.te_engine_get_stats(self._e, ctypes.byref(s)))
+        return s
+
+    def destroy(self):
+        if self._e is not None and self._e.value:
+            _check(_lib.te_engine_destroy(self._e))
+        self._e = None
+        self._keep = {}
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.destroy()
+
+
+def te_batch_run(groups, m=40, hbm_budget=0, max_jobs=0, shape=None, update_rows_per_thread=0, profile=False,
+                 options=None, stream=None):
+    """te_batch_create / add / launch / result / destroy over `groups`, a list of
+    (Hamiltonian, [v0 tensors], t, tol).  Returns (outputs per group, [(te_result, status)] in
+    submission order, te_engine_stats)."""
+    import torch
+    flags = TE_ENGINE_PROFILE if profile else 0
+    cfg = _engine_config(m, max_jobs, 0, shape, update_rows_per_thread, flags, options)
+    b = _P()
+    st = ctypes.c_void_p(0) if stream is None else _stream(stream)
+    _check(_lib.te_batch_create(ctypes.byref(b), ctypes.byref(cfg), st))
+    outs = []
+    try:
+        n_total = 0
+        for H, vs, t, tol in groups:
+            o = [torch.empty_like(v) for v in vs]
+            pv = (_P * len(vs))(*[_dev_c128(v, "v0", H.dim).value for v in vs])
+            po = (_P * len(vs))(*[_dev_c128(x, "out", H.dim).value for x in o])
+            first = _I()
+            _check(_lib.te_batch_add(b, H.handle, len(vs), pv, po, float(t), float(tol), ctypes.byref(first)))
+            outs.append(o)
+            n_total += len(vs)
+        stats = te_engine_stats()
+        _check(_lib.te_batch_launch(b, int(hbm_budget), ctypes.byref(stats)))
+        results = []
+        for i in range(n_total):
+            r, s = te_result(), _I()
+            _check(_lib.te_batch_result(b, i, ctypes.byref(r), ctypes.byref(s)))
+            results.append((r, s.value))
+    finally:
+        _lib.te_batch_destroy(b)
+    return outs, results, stats
 
 
 def exported_symbols():

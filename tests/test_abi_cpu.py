@@ -13,7 +13,7 @@ HEADER = os.path.join(ROOT, "include", "te.h")
 
 def header_functions():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:te_status|void|size_t|const char\*)\s+(te_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:te_status|void|size_t|uint64_t|const char\*)\s+(te_\w+)\s*\(", text, re.M)))
 
 
 def test_header_declares_the_boundary():
