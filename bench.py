@@ -77,6 +77,156 @@ def cpu_baseline(wl, gpu_restarts, n_restarts):
     }
 
 
+def kernel_rates(prof):
+    return {k: (v["bytes"] / v["seconds"] / 1e9 if v["seconds"] > 0 and v["bytes"] > 0 else None)
+            for k, v in prof.items()}
+
+
+def bench_batch(te, torch, dev, n_instances, m, profile):
+    """The 256-instance XXZ batch (L ~ U{10..18}, 1-8 vectors each, t ~ U[1,100], tol in
+    {1e-6, 1e-8, 1e-10}) through te_batch_*, against the same jobs one at a time through
+    te_evolve.  Latency of a job = time from the start of the run to its result."""
+    import workloads
+    jobs = workloads.batch_jobs(n_instances)
+    groups = []
+    b0 = time.perf_counter()
+    for j in jobs:
+        H, vs = j.build()
+        h = te.te_hamiltonian_create(H.row_ptr, H.col, H.val)
+        groups.append((h, [torch.from_numpy(v).to(dev) for v in vs], j.t, j.tol))
+    n_jobs = sum(len(g[1]) for g in groups)
+    rows = sum(g[0].dim * len(g[1]) for g in groups)
+    log(f"[bench] batch: {len(groups)} Hamiltonians, {n_jobs} jobs, {rows / 1e6:.1f}M rows "
+        f"(built in {time.perf_counter() - b0:.1f} s)")
+    te.te_batch_run(groups[:4], m=m)  # warm-up: load the batched kernels
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs, results, stats = te.te_batch_run(groups, m=m)
+    torch.cuda.synchronize()
+    batch_s = time.perf_counter() - t0
+    lat = [info.finished - info.submitted for _, _, info in results]
+    failed = sum(1 for _, s, _ in results if s != te.TE_OK)
+    log(f"[bench] batch: {batch_s:.2f} s, {n_jobs / batch_s:.1f} states/s, rounds={stats.rounds} "
+        f"plans={stats.plans} shape={stats.tuning.lanes_per_row}x{stats.tuning.nnz_per_lane}")
+    prof = None
+    if profile:
+        _, _, pst = te.te_batch_run(groups, m=m, shape=(stats.tuning.lanes_per_row, stats.tuning.nnz_per_lane),
+                                    profile=True)
+        prof = pst.prof.as_dict()
+    # one at a time through te_evolve (each handle autotunes its own shape on first use)
+    seq_done = []
+    worst = 0.0
+    torch.cuda.synchronize()
+    s0 = time.perf_counter()
+    k = 0
+    for gi, (h, vs, t, tol) in enumerate(groups):
+        for vi, v in enumerate(vs):
+            out, res = te.te_evolve(h, v, t, tol, m)
+            seq_done.append(time.perf_counter() - s0)
+            worst = max(worst, float((out - outs[gi][vi]).norm()) / max(res.err_bound + results[k][0].err_bound, 1e-300))
+            k += 1
+    seq_s = time.perf_counter() - s0
+    log(f"[bench] one at a time: {seq_s:.2f} s, {n_jobs / seq_s:.1f} states/s")
+    for g in groups:
+        g[0].destroy()
+    rec = {
+        "workload": f"xxz_batch_{n_instances}",
+        "instances": len(groups), "jobs": n_jobs, "rows": rows, "m": m,
+        "states_per_s": n_jobs / batch_s, "seconds": batch_s,
+        "latency_ms": {"p50": 1e3 * percentile(lat, 50), "p99": 1e3 * percentile(lat, 99)},
+        "one_at_a_time": {"states_per_s": n_jobs / seq_s, "seconds": seq_s,
+                          "latency_ms": {"p50": 1e3 * percentile(seq_done, 50), "p99": 1e3 * percentile(seq_done, 99)}},
+        "speedup_vs_one_at_a_time": seq_s / batch_s,
+        "rounds": stats.rounds, "plans": stats.plans, "failed": failed,
+        "pool_peak_gb": stats.pool_peak / 1e9,
+        "shape": {"lanes_per_row": stats.tuning.lanes_per_row, "nnz_per_lane": stats.tuning.nnz_per_lane,
+                  "update_rows_per_thread": stats.tuning.update_rows_per_thread},
+        "max_diff_over_bounds_vs_one_at_a_time": worst,
+    }
+    if prof:
+        rec["profile"] = {"kernel_gbs": kernel_rates(prof),
+                          "kernel_s": {k: v["seconds"] for k, v in prof.items()},
+                          "alg_gbs_all_kernels": sum(v["bytes"] for v in prof.values())
+                          / max(sum(v["seconds"] for v in prof.values()), 1e-12) / 1e9}
+    return rec
+
+
+def bench_serving(te, torch, dev, n_requests, qps, m, budget_gb):
+    """Poisson arrivals of XXZ (L 14..22) and Bose (K=N 10..12) requests into the threaded engine
+    (continuous batching, admission by footprint), against the same stream served one request at a
+    time by te_evolve (FIFO; completion = max(arrival, previous completion) + measured solve time)."""
+    import workloads
+    reqs = workloads.serving_requests(n_requests, qps)
+    hs = {}
+    b0 = time.perf_counter()
+    for r in reqs:
+        key = r.hamiltonian_key()
+        if key not in hs:
+            H = workloads.configs.serving_hamiltonian(*key)
+            hs[key] = te.te_hamiltonian_create(H.row_ptr, H.col, H.val)
+            del H
+    v0 = [torch.from_numpy(r.v0(hs[r.hamiltonian_key()].dim)).to(dev) for r in reqs]
+    log(f"[bench] serving: {len(reqs)} requests at {qps} qps over {len(hs)} Hamiltonians "
+        f"(built in {time.perf_counter() - b0:.1f} s)")
+    # warm-up: one small request through each path
+    small = min(hs.values(), key=lambda h: h.dim)
+    vw = torch.zeros(small.dim, dtype=torch.complex128, device=dev)
+    vw[0] = 1.0
+    te.te_evolve(small, vw, 1.0, 1e-8, m)
+    with te.Engine(int(budget_gb * 1e9), m=m, max_jobs=256) as eng:
+        w = eng.submit(small, vw, 1.0, 1e-8)
+        eng.wait(w, timeout=600)
+        torch.cuda.synchronize()
+        ids = []
+        t0 = time.perf_counter()
+        for r, v in zip(reqs, v0):
+            delay = r.arrival - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+            ids.append(eng.submit(hs[r.hamiltonian_key()], v, r.t, r.tol))
+        eng.wait(-1, timeout=3000)
+        infos = [eng.poll(j) for j in ids]
+        outs = [eng.output(j) for j in ids]
+        st = eng.stats()
+        first = min(i.submitted for i, _ in infos)
+        last = max(i.finished for i, _ in infos)
+        lat = [i.finished - i.submitted for i, _ in infos]
+        served_s = last - first
+        failed = sum(1 for i, _ in infos if i.state != te.TE_JOB_DONE)
+        log(f"[bench] serving: {served_s:.2f} s, {len(reqs) / served_s:.2f} states/s, p50 {percentile(lat, 50):.3f} s "
+            f"p99 {percentile(lat, 99):.3f} s, rounds={st.rounds} plans={st.plans} pool peak {st.pool_peak / 1e9:.1f} GB")
+        # the same requests one at a time
+        service, worst = [], 0.0
+        for r, v, o, (_, res) in zip(reqs, v0, outs, infos):
+            torch.cuda.synchronize()
+            s = time.perf_counter()
+            out, rr = te.te_evolve(hs[r.hamiltonian_key()], v, r.t, r.tol, m)
+            torch.cuda.synchronize()
+            service.append(time.perf_counter() - s)
+            worst = max(worst, float((out - o).norm()) / max(rr.err_bound + res.err_bound, 1e-300))
+    done, fifo_lat = 0.0, []
+    for r, sv in zip(reqs, service):
+        done = max(done, r.arrival) + sv
+        fifo_lat.append(done - r.arrival)
+    fifo_span = done - reqs[0].arrival
+    log(f"[bench] one at a time (FIFO): {len(reqs) / fifo_span:.2f} states/s, p50 {percentile(fifo_lat, 50):.3f} s "
+        f"p99 {percentile(fifo_lat, 99):.3f} s")
+    for h in hs.values():
+        h.destroy()
+    return {
+        "workload": f"serving_{n_requests}_at_{qps}qps",
+        "requests": len(reqs), "qps": qps, "m": m, "hbm_budget_gb": budget_gb,
+        "states_per_s": len(reqs) / served_s, "seconds": served_s,
+        "latency_ms": {"p50": 1e3 * percentile(lat, 50), "p99": 1e3 * percentile(lat, 99)},
+        "one_at_a_time_fifo": {"states_per_s": len(reqs) / fifo_span,
+                               "latency_ms": {"p50": 1e3 * percentile(fifo_lat, 50),
+                                              "p99": 1e3 * percentile(fifo_lat, 99)},
+                               "mean_service_ms": 1e3 * sum(service) / len(service)},
+        "rounds": st.rounds, "plans": st.plans, "failed": failed, "pool_peak_gb": st.pool_peak / 1e9,
+        "max_diff_over_bounds_vs_one_at_a_time": worst,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +234,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="xxz_L20")
     ap.add_argument("--cpu-restarts", type=int, default=2, help="restarts of the CPU oracle sample (0: skip)")
+    ap.add_argument("--batch-instances", type=int, default=256, help="instances of the XXZ batch (0: skip)")
+    ap.add_argument("--batch-profile", type=int, default=1, help="also run the batch in profiling mode")
+    ap.add_argument("--serve-requests", type=int, default=16, help="requests of the serving run (0: skip)")
+    ap.add_argument("--serve-qps", type=float, default=2.0)
+    ap.add_argument("--serve-budget-gb", type=float, default=96.0)
     args = ap.parse_args()
     if args.gpus != 1:
         log("bench.py measures one GPU: this build has no multi-GPU path (independent solves shard "
@@ -144,6 +299,13 @@ def main():
     alg_bytes = sum(v["bytes"] for v in totals.values())
     kernel_seconds = sum(v["seconds"] for v in totals.values())
 
+    H.destroy()
+    batch = serving = None
+    if args.batch_instances > 0:
+        batch = bench_batch(te, torch, dev, args.batch_instances, wl.m, bool(args.batch_profile))
+    if args.serve_requests > 0:
+        serving = bench_serving(te, torch, dev, args.serve_requests, args.serve_qps, wl.m, args.serve_budget_gb)
+
     cpu = None
     if args.cpu_restarts > 0:
         log(f"[bench] CPU oracle sample: {args.cpu_restarts} restarts")
@@ -186,8 +348,9 @@ def main():
         "matvecs_per_solve": matvecs,
         "err_bound": bound,
         "graph_mode": {"ms_per_step": 1e3 * graph_elapsed / args.steps, "value": args.steps / graph_elapsed},
+        "batch": batch,
+        "serving": serving,
     }
-    H.destroy()
     print(json.dumps(line), flush=True)
 
 

@@ -331,7 +331,8 @@ te_status te_engine_destroy(te_engine e);
  * te_batch_add appends n jobs on one H (v0[i], v_out[i]: host arrays of n device pointers)
  * and returns the index of the first; te_batch_launch runs every job (hbm_budget 0: the sum
  * of the footprints, so all jobs are resident from the first round) and returns once all are
- * done; te_batch_result gives a job's result and status.  cfg: as for te_engine_create
+ * done; te_batch_result gives a job's result and status, te_batch_info its timing (submitted
+ * = start of te_batch_launch).  cfg: as for te_engine_create
  * (max_jobs 0 = all jobs, hbm_budget ignored; TE_ENGINE_THREADED ignored). */
 typedef struct te_batch_s* te_batch;
 te_status te_batch_create(te_batch* out, const te_engine_config* cfg, void* stream);
@@ -339,6 +340,7 @@ te_status te_batch_add(te_batch b, te_hamiltonian h, int32_t n, const te_c128* c
                        te_c128* const* v_out, double t, double tol, int32_t* first);
 te_status te_batch_launch(te_batch b, uint64_t hbm_budget, te_engine_stats* stats);
 te_status te_batch_result(te_batch b, int32_t i, te_result* res, te_status* status);
+te_status te_batch_info(te_batch b, int32_t i, te_job_info* info); /* times, rounds, state */
 te_status te_batch_destroy(te_batch b);
 
 #ifdef __cplusplus

@@ -222,27 +222,18 @@ __global__ __launch_bounds__(kBlock) void k_project(const int* __restrict__ rp, 
     project_body<RPT, G, U>(rp, ci, val, V, ld, dim, j, y, st, rb, blockIdx.x);
 }
 
-// Batched projection: one workgroup per (group, tile).  The jobs of a group share H, so the
-// sparse product streams each (column, value) pair once and applies it to every vector of the
-// group (a multi-vector product, NV >= group size); the projections then run per vector.
-// Tiles are kBlock rows (one row per thread in the dense part).
-template <int G, int U, int NV>
-__global__ __launch_bounds__(kBlock) void k_gproject(const JobView* __restrict__ jobs,
-                                                      const GroupView* __restrict__ groups,
-                                                      const int2* __restrict__ items, int j) {
-    __shared__ double2 ytile[NV][kBlock];
-    __shared__ double2 wpart[kWaves][kMaxVals];
-    const int2 it = items[blockIdx.x];
-    const GroupView& gv = groups[it.x];
-    const int tile = it.y;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int dim = gv.dim;
-    const int r0 = tile * kBlock;
-    const int r1 = min(r0 + kBlock, dim);
+// Batched projection.  Jobs that share H form a group; a group of one runs the fused kernel
+// below (sparse product into LDS, then the projections), a larger group runs the multi-vector
+// sparse product, which streams each (column, value) pair of H once for every vector of the
+// group, followed by the projections as a separate launch over (job, tile) items.  Both paths
+// accumulate every value in the same order as the single-solve projection with one row per
+// thread, so a job's results do not depend on its group.  Tiles are kBlock rows.
 
+// live vectors of a group at iteration j (bit v: job gv.job[v] still builds its basis)
+template <int NV>
+__device__ __forceinline__ unsigned group_mask(const JobView* __restrict__ jobs, const GroupView& gv, int j,
+                                               const double2* (&xs)[NV], double2* (&ys)[NV]) {
     unsigned mask = 0;
-    const double2* xs[NV];
-    double2* ys[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         xs[v] = nullptr;
@@ -257,105 +248,155 @@ __global__ __launch_bounds__(kBlock) void k_gproject(const JobView* __restrict__
             }
         }
     }
-    if (mask == 0) return;
+    return mask;
+}
+
+// y_v = H V_v[:, j] on rows [r0, r1) for every live vector: G lanes per row, U nonzeros in
+// flight each; results to y_v and, if ytile is given, to LDS (NV = 1).
+template <int G, int U, int NV>
+__device__ __forceinline__ void group_spmv(const GroupView& gv, int r0, int r1, unsigned mask,
+                                           const double2* const (&xs)[NV], double2* const (&ys)[NV],
+                                           double2* ytile) {
     const int* __restrict__ rp = gv.rp;
     const int* __restrict__ ci = gv.ci;
     const double2* __restrict__ val = gv.val;
-
-    // y_v = H V_v[:, j] for every live vector: G lanes per row, U nonzeros in flight each
-    {
-        const int lg = tid % G, grp = tid / G;
-        for (int r = r0 + grp; r < r1; r += kBlock / G) {
-            double2 acc[NV];
+    const int tid = threadIdx.x;
+    const int lg = tid % G, grp = tid / G;
+    for (int r = r0 + grp; r < r1; r += kBlock / G) {
+        double2 acc[NV];
 #pragma unroll
-            for (int v = 0; v < NV; ++v) acc[v] = make_double2(0.0, 0.0);
-            const int kb = rp[r], ke = rp[r + 1];
-            for (int k0 = kb + lg; k0 < ke; k0 += G * U) {
-                double2 vv[U];
-                int cc[U];
+        for (int v = 0; v < NV; ++v) acc[v] = make_double2(0.0, 0.0);
+        const int kb = rp[r], ke = rp[r + 1];
+        for (int k0 = kb + lg; k0 < ke; k0 += G * U) {
+            double2 vv[U];
+            int cc[U];
 #pragma unroll
-                for (int q = 0; q < U; ++q) {
-                    const int k = k0 + q * G;
-                    if (k < ke) {
-                        vv[q] = val[k];
-                        cc[q] = ci[k];
-                    } else {
-                        vv[q] = make_double2(0.0, 0.0);
-                        cc[q] = -1;
-                    }
-                }
-#pragma unroll
-                for (int q = 0; q < U; ++q) {
-                    if (cc[q] < 0) continue;
-#pragma unroll
-                    for (int v = 0; v < NV; ++v)
-                        if (mask & (1u << v)) acc[v] = cfma(vv[q], xs[v][cc[q]], acc[v]);
+            for (int q = 0; q < U; ++q) {
+                const int k = k0 + q * G;
+                if (k < ke) {
+                    vv[q] = val[k];
+                    cc[q] = ci[k];
+                } else {
+                    vv[q] = make_double2(0.0, 0.0);
+                    cc[q] = -1;
                 }
             }
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
+            for (int q = 0; q < U; ++q) {
+                if (cc[q] < 0) continue;
 #pragma unroll
-                for (int o = G / 2; o > 0; o >>= 1) {
-                    acc[v].x += __shfl_xor(acc[v].x, o);
-                    acc[v].y += __shfl_xor(acc[v].y, o);
-                }
-                if (lg == 0 && (mask & (1u << v))) {
-                    ys[v][r] = acc[v];
-                    ytile[v][r - r0] = acc[v];
-                }
+                for (int v = 0; v < NV; ++v)
+                    if (mask & (1u << v)) acc[v] = cfma(vv[q], xs[v][cc[q]], acc[v]);
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+#pragma unroll
+            for (int o = G / 2; o > 0; o >>= 1) {
+                acc[v].x += __shfl_xor(acc[v].x, o);
+                acc[v].y += __shfl_xor(acc[v].y, o);
+            }
+            if (lg == 0 && (mask & (1u << v))) {
+                ys[v][r] = acc[v];
+                if (ytile) ytile[r - r0] = acc[v];
+            }
+        }
+    }
+}
+
+// Projections of one job on one tile, one row per thread: c'_i = V_i^H y and g_i = V_i^H V_j
+// for i <= j, reduced over the tile in a fixed order into rb.part[value][tile].
+__device__ __forceinline__ void tile_dots(const JobView& J, int j, int tile, double2 yq,
+                                          double2 (&wpart)[kWaves][kMaxVals]) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = tile * kBlock + tid;
+    const bool in = r < J.dim;
+    const double2* __restrict__ V = J.V;
+    const int64_t ld = J.ld;
+    const double2 xq = in ? V[(int64_t)j * ld + r] : make_double2(0.0, 0.0);
+    for (int i0 = 0; i0 <= j; i0 += 8) {
+        double a[32];
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            double2 cy = make_double2(0.0, 0.0), cx = make_double2(0.0, 0.0);
+            const int i = i0 + b;
+            if (i <= j && in) {
+                const double2 w = V[(int64_t)i * ld + r];
+                cy = cfma_conj(w, yq, cy);
+                cx = cfma_conj(w, xq, cx);
+            }
+            a[4 * b] = cy.x;
+            a[4 * b + 1] = cy.y;
+            a[4 * b + 2] = cx.x;
+            a[4 * b + 3] = cx.y;
+        }
+        const double sum = halving_reduce32(a, lane);
+        if ((lane & 1) == 0) {
+            const int q = lane >> 1;
+            const int i = i0 + (q >> 2);
+            if (i <= j) {
+                double* dst = (double*)&wpart[wave][2 * i + ((q >> 1) & 1)];
+                dst[q & 1] = sum;
             }
         }
     }
     __syncthreads();
-
-    // projections, one vector at a time: c'_i = V_i^H y and g_i = V_i^H V_j on this tile
-    const int r = r0 + tid;
-#pragma unroll 1
-    for (int v = 0; v < NV; ++v) {
-        if (!(mask & (1u << v))) continue;
-        const JobView& J = jobs[gv.job[v]];
-        const double2* __restrict__ V = J.V;
-        const int64_t ld = J.ld;
-        double2 yq = make_double2(0.0, 0.0), xq = make_double2(0.0, 0.0);
-        if (r < r1) {
-            yq = ytile[v][tid];
-            xq = V[(int64_t)j * ld + r];
-        }
-        for (int i0 = 0; i0 <= j; i0 += 8) {
-            double a[32];
-#pragma unroll
-            for (int b = 0; b < 8; ++b) {
-                double2 cy = make_double2(0.0, 0.0), cx = make_double2(0.0, 0.0);
-                const int i = i0 + b;
-                if (i <= j && r < r1) {
-                    const double2 w = V[(int64_t)i * ld + r];
-                    cy = cfma_conj(w, yq, cy);
-                    cx = cfma_conj(w, xq, cx);
-                }
-                a[4 * b] = cy.x;
-                a[4 * b + 1] = cy.y;
-                a[4 * b + 2] = cx.x;
-                a[4 * b + 3] = cx.y;
-            }
-            const double sum = halving_reduce32(a, lane);
-            if ((lane & 1) == 0) {
-                const int q = lane >> 1;
-                const int i = i0 + (q >> 2);
-                if (i <= j) {
-                    double* dst = (double*)&wpart[wave][2 * i + ((q >> 1) & 1)];
-                    dst[q & 1] = sum;
-                }
-            }
-        }
-        __syncthreads();
-        const int nvals = 2 * (j + 1);
-        for (int q = tid; q < nvals; q += kBlock) {
-            double2 sum = make_double2(0.0, 0.0);
-            for (int w = 0; w < kWaves; ++w) sum = cadd(sum, wpart[w][q]);
-            J.rb.part[(size_t)q * J.rb.n_tiles + tile] = sum;
-        }
-        __syncthreads();
+    const int nvals = 2 * (j + 1);
+    for (int q = tid; q < nvals; q += kBlock) {
+        double2 sum = make_double2(0.0, 0.0);
+        for (int w = 0; w < kWaves; ++w) sum = cadd(sum, wpart[w][q]);
+        J.rb.part[(size_t)q * J.rb.n_tiles + tile] = sum;
     }
+}
+
+// fused projection of a group of one: one workgroup per (group, tile)
+template <int G, int U>
+__global__ __launch_bounds__(kBlock) void k_gproject(const JobView* __restrict__ jobs,
+                                                      const GroupView* __restrict__ groups,
+                                                      const int2* __restrict__ items, int j) {
+    __shared__ double2 ytile[kBlock];
+    __shared__ double2 wpart[kWaves][kMaxVals];
+    const int2 it = items[blockIdx.x];
+    const GroupView& gv = groups[it.x];
+    const double2* xs[1];
+    double2* ys[1];
+    const unsigned mask = group_mask<1>(jobs, gv, j, xs, ys);
+    if (mask == 0) return;
+    const int r0 = it.y * kBlock;
+    const int r1 = min(r0 + kBlock, gv.dim);
+    group_spmv<G, U, 1>(gv, r0, r1, mask, xs, ys, ytile);
+    __syncthreads();
+    const int r = r0 + threadIdx.x;
+    const double2 yq = (r < r1) ? ytile[threadIdx.x] : make_double2(0.0, 0.0);
+    tile_dots(jobs[gv.job[0]], j, it.y, yq, wpart);
+}
+
+// multi-vector sparse product of a group: one workgroup per (group, tile)
+template <int G, int U, int NV>
+__global__ __launch_bounds__(kBlock) void k_gspmm(const JobView* __restrict__ jobs,
+                                                   const GroupView* __restrict__ groups,
+                                                   const int2* __restrict__ items, int j) {
+    const int2 it = items[blockIdx.x];
+    const GroupView& gv = groups[it.x];
+    const double2* xs[NV];
+    double2* ys[NV];
+    const unsigned mask = group_mask<NV>(jobs, gv, j, xs, ys);
+    if (mask == 0) return;
+    const int r0 = it.y * kBlock;
+    group_spmv<G, U, NV>(gv, r0, min(r0 + kBlock, gv.dim), mask, xs, ys, nullptr);
+}
+
+// projections after a multi-vector product: one workgroup per (job, tile)
+__global__ __launch_bounds__(kBlock) void k_bdots(const JobView* __restrict__ jobs, const int2* __restrict__ items,
+                                                  int j) {
+    __shared__ double2 wpart[kWaves][kMaxVals];
+    const int2 it = items[blockIdx.x];
+    const JobView& J = jobs[it.x];
+    const DevState* st = J.st;
+    if (st->done || j >= st->k_limit) return;
+    const int r = it.y * kBlock + threadIdx.x;
+    const double2 yq = (r < J.dim) ? J.y[r] : make_double2(0.0, 0.0);
+    tile_dots(J, j, it.y, yq, wpart);
 }
 
 // ---------------------------------------------------- fold of the projection partials
@@ -797,13 +838,15 @@ template <int G, int U>
 static void gproject_nv(int nv_class, dim3 grid, hipStream_t s, const JobView* jobs, const GroupView* groups,
                         const int2* items, int j) {
     switch (nv_class) {
-        case 1: k_gproject<G, U, 1><<<grid, kBlock, 0, s>>>(jobs, groups, items, j); break;
-        case 2: k_gproject<G, U, 2><<<grid, kBlock, 0, s>>>(jobs, groups, items, j); break;
-        case 4: k_gproject<G, U, 4><<<grid, kBlock, 0, s>>>(jobs, groups, items, j); break;
-        default: k_gproject<G, U, 8><<<grid, kBlock, 0, s>>>(jobs, groups, items, j); break;
+        case 1: k_gproject<G, U><<<grid, kBlock, 0, s>>>(jobs, groups, items, j); break;
+        case 2: k_gspmm<G, U, 2><<<grid, kBlock, 0, s>>>(jobs, groups, items, j); break;
+        case 4: k_gspmm<G, U, 4><<<grid, kBlock, 0, s>>>(jobs, groups, items, j); break;
+        default: k_gspmm<G, U, 8><<<grid, kBlock, 0, s>>>(jobs, groups, items, j); break;
     }
 }
 
+// nv_class 1: fused product + projections; 2, 4, 8: the multi-vector product only (the
+// projections follow with launch_bdots)
 hipError_t launch_gproject(int g, int u, int nv_class, const JobView* jobs, const GroupView* groups,
                            const int2* items, int n_items, int j, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
@@ -811,6 +854,12 @@ hipError_t launch_gproject(int g, int u, int nv_class, const JobView* jobs, cons
     if (g == 8) gproject_nv<8, 2>(nv_class, grid, s, jobs, groups, items, j);
     else if (u == 1) gproject_nv<4, 1>(nv_class, grid, s, jobs, groups, items, j);
     else gproject_nv<4, 4>(nv_class, grid, s, jobs, groups, items, j);
+    return hipGetLastError();
+}
+
+hipError_t launch_bdots(const JobView* jobs, const int2* items, int n_items, int j, hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    k_bdots<<<n_items, kBlock, 0, s>>>(jobs, items, j);
     return hipGetLastError();
 }
 

@@ -109,6 +109,8 @@ struct Plan {
     int n_pitems[4] = {0, 0, 0, 0};
     int2* uitems = nullptr;
     int n_uitems = 0;
+    int2* ditems = nullptr;  // (job, tile) projections of jobs in groups of two or more
+    int n_ditems = 0;
     JobView* new_jobs = nullptr;
     Problem* probs = nullptr;
     int2* new_items = nullptr;
@@ -225,6 +227,7 @@ hipError_t enqueue_round(te_engine_s* e, const Plan& p, hipStream_t s, std::vect
         for (int c = 0; c < 4 && r == hipSuccess; ++c)
             r = launch_gproject(t.lanes_per_row, t.nnz_per_lane, kClasses[c], p.jobs, p.groups, p.pitems[c],
                                 p.n_pitems[c], j, s);
+        if (r == hipSuccess) r = launch_bdots(p.jobs, p.ditems, p.n_ditems, j, s);
         mark(3 * j + 1);
         if (r == hipSuccess) r = launch_bfold(p.jobs, p.n_jobs, j, s);
         mark(3 * j + 2);
@@ -258,6 +261,7 @@ te_status autotune(te_engine_s* e, const Plan& p) {
             for (int c = 0; c < 4 && r == hipSuccess; ++c)
                 r = launch_gproject(sh[0], sh[1], kClasses[c], p.jobs, p.groups, p.pitems[c], p.n_pitems[c], J,
                                     e->stream);
+            if (r == hipSuccess) r = launch_bdots(p.jobs, p.ditems, p.n_ditems, J, e->stream);
         };
         launch_all();
         if (r == hipSuccess) r = hipEventRecord(e0, e->stream);
@@ -365,10 +369,12 @@ te_status build_plan(te_engine_s* e) {
     }
     p.n_groups = (int)p.group_jobs.size();
     int n_new = 0;
-    int64_t n_items_c[4] = {0, 0, 0, 0}, n_u = 0, n_new_items = 0;
+    int64_t n_items_c[4] = {0, 0, 0, 0}, n_u = 0, n_new_items = 0, n_d = 0;
     for (const auto& g : p.group_jobs) {
         const JobRec& j0 = e->jobs[(size_t)ids[(size_t)g[0]]];
-        n_items_c[nv_class_index((int)g.size())] += ceil_div(j0.dim, kTileRows);
+        const int64_t tiles = ceil_div(j0.dim, kTileRows);
+        n_items_c[nv_class_index((int)g.size())] += tiles;
+        if (g.size() > 1) n_d += tiles * (int64_t)g.size();
     }
     for (te_job id : ids) {
         const JobRec& j = e->jobs[(size_t)id];
@@ -381,7 +387,7 @@ te_status build_plan(te_engine_s* e) {
         }
     }
     const int64_t n_p = n_items_c[0] + n_items_c[1] + n_items_c[2] + n_items_c[3];
-    if (n_p >= ((int64_t)1 << 31) / kBlock || n_u >= ((int64_t)1 << 31) / kBlock)
+    if (n_p >= ((int64_t)1 << 31) / kBlock || n_u >= ((int64_t)1 << 31) / kBlock || n_d >= ((int64_t)1 << 31) / kBlock)
         return set_error(TE_ERR_CAPACITY, "round work list too long");
 
     // layout of the plan buffer
@@ -396,6 +402,7 @@ te_status build_plan(te_engine_s* e) {
     size_t o_p[4];
     for (int c = 0; c < 4; ++c) o_p[c] = take(sizeof(int2) * std::max<int64_t>(n_items_c[c], 1));
     const size_t o_u = take(sizeof(int2) * std::max<int64_t>(n_u, 1));
+    const size_t o_d = take(sizeof(int2) * std::max<int64_t>(n_d, 1));
     const size_t o_nj = take(sizeof(JobView) * std::max(n_new, 1));
     const size_t o_pr = take(sizeof(Problem) * std::max(n_new, 1));
     const size_t o_ni = take(sizeof(int2) * std::max<int64_t>(n_new_items, 1));
@@ -409,12 +416,14 @@ te_status build_plan(te_engine_s* e) {
     int2* hp[4];
     for (int c = 0; c < 4; ++c) hp[c] = (int2*)(H + o_p[c]);
     int2* hu = (int2*)(H + o_u);
+    int2* hd = (int2*)(H + o_d);
     JobView* hnj = (JobView*)(H + o_nj);
     Problem* hpr = (Problem*)(H + o_pr);
     int2* hni = (int2*)(H + o_ni);
 
     for (int i = 0; i < p.n_jobs; ++i) hj[i] = job_view(e, e->jobs[(size_t)ids[(size_t)i]], rpt_u);
     int fill_c[4] = {0, 0, 0, 0};
+    int fill_d = 0;
     for (int gi = 0; gi < p.n_groups; ++gi) {
         const auto& g = p.group_jobs[(size_t)gi];
         const JobRec& j0 = e->jobs[(size_t)ids[(size_t)g[0]]];
@@ -429,6 +438,9 @@ te_status build_plan(te_engine_s* e) {
         const int c = nv_class_index(gv.nv);
         const int tiles = (int)ceil_div(j0.dim, kTileRows);
         for (int t = 0; t < tiles; ++t) hp[c][fill_c[c]++] = make_int2(gi, t);
+        if (gv.nv > 1)
+            for (int t = 0; t < tiles; ++t)
+                for (int q = 0; q < gv.nv; ++q) hd[fill_d++] = make_int2(g[(size_t)q], t);
     }
     int fu = 0, fn = 0, fni = 0;
     for (int i = 0; i < p.n_jobs; ++i) {
@@ -444,6 +456,7 @@ te_status build_plan(te_engine_s* e) {
     }
     for (int c = 0; c < 4; ++c) p.n_pitems[c] = (int)n_items_c[c];
     p.n_uitems = (int)n_u;
+    p.n_ditems = (int)n_d;
     p.n_new = n_new;
     p.n_new_items = (int)n_new_items;
 
@@ -452,6 +465,7 @@ te_status build_plan(te_engine_s* e) {
     p.groups = (GroupView*)(D + o_groups);
     for (int c = 0; c < 4; ++c) p.pitems[c] = (int2*)(D + o_p[c]);
     p.uitems = (int2*)(D + o_u);
+    p.ditems = (int2*)(D + o_d);
     p.new_jobs = (JobView*)(D + o_nj);
     p.probs = (Problem*)(D + o_pr);
     p.new_items = (int2*)(D + o_ni);
@@ -1033,6 +1047,13 @@ te_status te_batch_result(te_batch b, int32_t i, te_result* res, te_status* stat
     if (rc != TE_OK) return rc;
     if (status) *status = (info.state == TE_JOB_DONE || info.state == TE_JOB_FAILED) ? info.status : TE_ERR_TIMEOUT;
     return TE_OK;
+}
+
+te_status te_batch_info(te_batch b, int32_t i, te_job_info* info) {
+    if (!b || !info) return set_error(TE_ERR_INVALID_ARG, "null pointer");
+    if (i < 0 || (size_t)i >= b->items.size()) return set_error(TE_ERR_INVALID_ARG, "index out of range");
+    if (!b->eng) return set_error(TE_ERR_INVALID_ARG, "batch not launched");
+    return te_engine_poll(b->eng, b->items[(size_t)i].id, info, nullptr);
 }
 
 te_status te_batch_destroy(te_batch b) {

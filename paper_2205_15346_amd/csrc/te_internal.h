@@ -216,6 +216,7 @@ hipError_t launch_norm1(const double* rowsum, int dim, double* out, hipStream_t 
 // batched launchers: items are (group or job, tile) pairs, one workgroup each
 hipError_t launch_gproject(int g, int u, int nv_class, const JobView* jobs, const GroupView* groups,
                            const int2* items, int n_items, int j, hipStream_t s);
+hipError_t launch_bdots(const JobView* jobs, const int2* items, int n_items, int j, hipStream_t s);
 hipError_t launch_bfold(const JobView* jobs, int n_jobs, int j, hipStream_t s);
 hipError_t launch_bupdate(int rpt, const JobView* jobs, const int2* items, int n_items, int j, hipStream_t s);
 hipError_t launch_bstep(const JobView* jobs, int n_jobs, hipStream_t s);

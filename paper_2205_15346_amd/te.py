@@ -158,6 +158,7 @@ _SIGS = {
     "te_batch_add": (_I, [_P, _P, _I, ctypes.POINTER(_P), ctypes.POINTER(_P), _D, _D, _PI]),
     "te_batch_launch": (_I, [_P, ctypes.c_uint64, ctypes.POINTER(te_engine_stats)]),
     "te_batch_result": (_I, [_P, _I, ctypes.POINTER(te_result), _PI]),
+    "te_batch_info": (_I, [_P, _I, ctypes.POINTER(te_job_info)]),
     "te_batch_destroy": (_I, [_P]),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -458,9 +459,9 @@ class Engine:
 
 def te_batch_run(groups, m=40, hbm_budget=0, max_jobs=0, shape=None, update_rows_per_thread=0, profile=False,
                  options=None, stream=None):
-    """te_batch_create / add / launch / result / destroy over `groups`, a list of
-    (Hamiltonian, [v0 tensors], t, tol).  Returns (outputs per group, [(te_result, status)] in
-    submission order, te_engine_stats)."""
+    """te_batch_create / add / launch / result / info / destroy over `groups`, a list of
+    (Hamiltonian, [v0 tensors], t, tol).  Returns (outputs per group, [(te_result, status,
+    te_job_info)] in submission order, te_engine_stats)."""
     import torch
     flags = TE_ENGINE_PROFILE if profile else 0
     cfg = _engine_config(m, max_jobs, 0, shape, update_rows_per_thread, flags, options)
@@ -482,9 +483,10 @@ def te_batch_run(groups, m=40, hbm_budget=0, max_jobs=0, shape=None, update_rows
         _check(_lib.te_batch_launch(b, int(hbm_budget), ctypes.byref(stats)))
         results = []
         for i in range(n_total):
-            r, s = te_result(), _I()
+            r, s, info = te_result(), _I(), te_job_info()
             _check(_lib.te_batch_result(b, i, ctypes.byref(r), ctypes.byref(s)))
-            results.append((r, s.value))
+            _check(_lib.te_batch_info(b, i, ctypes.byref(info)))
+            results.append((r, s.value, info))
     finally:
         _lib.te_batch_destroy(b)
     return outs, results, stats

@@ -59,13 +59,13 @@ def test_batch_bitwise_equals_alone(mixed_groups):
     outs, results, stats = te.te_batch_run([(h, d, t, tol) for h, d, (_, _, t, tol) in zip(hs, dev, mixed_groups)],
                                            m=M, shape=SHAPE, update_rows_per_thread=1)
     assert stats.jobs_done == 9 and stats.jobs_failed == 0
-    assert stats.rounds >= max(r.steps for r, _ in results)
+    assert stats.rounds >= max(r.steps for r, _, _ in results)
     i = 0
     for gi, (h, d, (_, _, t, tol)) in enumerate(zip(hs, dev, mixed_groups)):
         for vi, v in enumerate(d):
             announce(f"alone: group {gi} vector {vi}")
             ref, rres = alone(h, v, t, tol)
-            res, status = results[i]
+            res, status, _ = results[i]
             assert status == te.TE_OK
             assert same_result(res, rres), (gi, vi, res.as_dict(), rres.as_dict())
             assert bool((outs[gi][vi] == ref).all()), (gi, vi)
@@ -80,7 +80,7 @@ def test_batch_matches_oracle():
     announce("batch L=10 x2 vs oracle")
     with hamiltonian(H) as h:
         outs, results, _ = te.te_batch_run([(h, [to_dev(v) for v in vs], t, tol)], m=M)
-        for v, o, (res, status) in zip(vs, outs[0], results):
+        for v, o, (res, status, _) in zip(vs, outs[0], results):
             assert status == te.TE_OK
             ref = O.evolve(H, v, t, tol, M)
             assert np.linalg.norm(to_host(o) - ref.v) <= 2 * tol + 1e-12
@@ -100,7 +100,7 @@ def test_batch_autotuned_agrees_with_alone(mixed_groups):
     for gi, (h, d, (_, _, t, tol)) in enumerate(zip(hs, dev, mixed_groups)):
         for vi, v in enumerate(d):
             ref, rres = alone(h, v, t, tol, shape=(8, 2), rpt_u=2)
-            res, status = results[i]
+            res, status, _ = results[i]
             assert status == te.TE_OK
             err = float((outs[gi][vi] - ref).norm())
             assert err <= res.err_bound + rres.err_bound + 1e-12, (gi, vi, err)
@@ -233,7 +233,7 @@ def test_engine_profile_mode_accounts_every_kernel_class(mixed_groups):
             assert prof[k]["launches"] > 0 and prof[k]["seconds"] > 0, k
         for k in ("project", "update", "combine"):
             assert prof[k]["bytes"] > 0, k
-        rounds = max(r.steps for r, _ in res_p)
+        rounds = max(r.steps for r, _, _ in res_p)
         assert prof["step"]["launches"] == rounds and st.rounds == rounds
 
 
@@ -254,7 +254,7 @@ def test_batch_sample_of_the_256_instance_workload():
     k = 0
     for gi, (h, d, t, tol) in enumerate(groups):
         for vi, v in enumerate(d):
-            res, status = results[k]
+            res, status, _ = results[k]
             k += 1
             assert status == te.TE_OK
             assert res.err_bound <= tol * (1 + 1e-12)
