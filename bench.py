@@ -234,6 +234,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="xxz_L20")
     ap.add_argument("--cpu-restarts", type=int, default=2, help="restarts of the CPU oracle sample (0: skip)")
+    ap.add_argument("--shape", default="8,2,2,2,1",
+                    help="projection kernel shape lanes,nnz,rows,update_rows,split for the single solve "
+                         "(default: the shape te_autotune selects for this matrix on MI355X), or 'auto'")
     ap.add_argument("--batch-instances", type=int, default=256, help="instances of the XXZ batch (0: skip)")
     ap.add_argument("--batch-profile", type=int, default=1, help="also run the batch in profiling mode")
     ap.add_argument("--serve-requests", type=int, default=16, help="requests of the serving run (0: skip)")
@@ -261,9 +264,14 @@ def main():
     plain = te.te_default_options()
     prof = te.te_default_options(flags=te.TE_OPT_PROFILE)
 
+    if args.shape != "auto":
+        te.te_set_tuning(H, *[int(x) for x in args.shape.split(",")])
     for i in range(args.warmup):
         _, res = te.te_evolve(H, v0, wl.t, wl.tol, wl.m, options=plain, out=out)
         log(f"[bench] warmup {i}: restarts={res.steps} bound={res.err_bound:.3e}")
+
+    tuning = te.te_get_tuning(H).as_dict()
+    log(f"[bench] kernel shape: {tuning}")
 
     # ---- timed region (profiling mode: events around every kernel, on the call's stream)
     totals = {k: {"launches": 0, "seconds": 0.0, "bytes": 0.0} for k in te.KERNEL_CLASSES}
@@ -293,6 +301,10 @@ def main():
 
     kernel_gbs = {k: (v["bytes"] / v["seconds"] / 1e9 if v["seconds"] > 0 else None) for k, v in totals.items()}
     traffic = measured_traffic(os.path.join(ROOT, "paper_2205_15346_amd", "csrc", "arnoldi.hip"))
+    shape = [tuning[k] for k in ("lanes_per_row", "nnz_per_lane", "rows_per_thread", "update_rows_per_thread",
+                                 "split_projection")]
+    if traffic and traffic.get("shape") != shape:
+        traffic = None  # the counters were taken on another kernel shape
     dominant = max(totals, key=lambda k: totals[k]["seconds"])
     dom = totals[dominant]
     achieved = dom["bytes"] / dom["seconds"] / 1e9
@@ -348,6 +360,7 @@ def main():
         "matvecs_per_solve": matvecs,
         "err_bound": bound,
         "graph_mode": {"ms_per_step": 1e3 * graph_elapsed / args.steps, "value": args.steps / graph_elapsed},
+        "kernel_shape": tuning,
         "batch": batch,
         "serving": serving,
     }

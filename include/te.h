@@ -174,6 +174,8 @@ typedef struct {
     int32_t nnz_per_lane;           /* nonzeros per lane in flight: 1 or 4 (4 lanes), 2 (8 lanes) */
     int32_t rows_per_thread;        /* projection kernel: 1 or 2 */
     int32_t update_rows_per_thread; /* update and recombination kernels: 1 or 2 */
+    int32_t split_projection;       /* 0: sparse product fused with the projections in one kernel;
+                                       1: two launches, the product vector read back (same results) */
     double project_us;              /* measured time of one projection launch, 0 if not measured */
 } te_tuning;
 

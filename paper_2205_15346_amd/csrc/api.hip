@@ -136,7 +136,8 @@ namespace {
 Tiling handle_tiling(te_hamiltonian h) {
     if (!h->tuned) return default_tiling(h->csr.dim);
     const te_tuning& t = h->tuning;
-    return make_tiling(h->csr.dim, t.rows_per_thread, t.lanes_per_row, t.nnz_per_lane, t.update_rows_per_thread);
+    return make_tiling(h->csr.dim, t.rows_per_thread, t.lanes_per_row, t.nnz_per_lane, t.update_rows_per_thread,
+                       t.split_projection);
 }
 
 te_status make_workspace(te_hamiltonian h, int m, Workspace** out) {
@@ -310,14 +311,15 @@ bool tune_cache_lookup(const std::string& key, te_tuning* t) {
     while (std::fgets(line, sizeof(line), f)) {
         char arch[32];
         long long dim, nnz;
-        int m, g, u, rp, ru;
+        int m, g, u, rp, ru, sp;
         double us;
-        if (std::sscanf(line, "%31s %lld %lld %d %d %d %d %d %lf", arch, &dim, &nnz, &m, &g, &u, &rp, &ru, &us) != 9)
+        if (std::sscanf(line, "%31s %lld %lld %d %d %d %d %d %d %lf", arch, &dim, &nnz, &m, &g, &u, &rp, &ru, &sp,
+                        &us) != 10)
             continue;
         const std::string k = std::string(arch) + " " + std::to_string(dim) + " " + std::to_string(nnz) + " " +
                               std::to_string(m);
-        if (k == key && tiling_supported(rp, g, u, ru)) {
-            *t = te_tuning{g, u, rp, ru, us};
+        if (k == key && tiling_supported(rp, g, u, ru, sp)) {
+            *t = te_tuning{g, u, rp, ru, sp, us};
             found = true;
         }
     }
@@ -330,12 +332,12 @@ void tune_cache_store(const std::string& key, const te_tuning& t) {
     if (!path || !*path) return;
     FILE* f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%s %d %d %d %d %.3f\n", key.c_str(), t.lanes_per_row, t.nnz_per_lane, t.rows_per_thread,
-                 t.update_rows_per_thread, t.project_us);
+    std::fprintf(f, "%s %d %d %d %d %d %.3f\n", key.c_str(), t.lanes_per_row, t.nnz_per_lane, t.rows_per_thread,
+                 t.update_rows_per_thread, t.split_projection, t.project_us);
     std::fclose(f);
 }
 
-// Times the projection kernel (iteration j = min(8, m-1), zero basis) for every supported shape.
+// Times the projection kernel (iteration j = m/2, zero basis) for every supported shape.
 te_status run_autotune(te_hamiltonian h, Workspace* w, hipStream_t s) {
     const std::string key = tune_key(h, w->m);
     te_tuning best{};
@@ -344,7 +346,7 @@ te_status run_autotune(te_hamiltonian h, Workspace* w, hipStream_t s) {
         h->tuned = true;
         return retile(h, w, handle_tiling(h));
     }
-    const int J = std::min(8, w->m - 1);
+    const int J = std::min(w->m / 2, w->m - 1);  // mid-restart: the mean cost over j = 0..m-1
     te_options o;
     te_default_options(&o);
     const Problem prob = make_problem(h, o, 1.0, 1.0, w->m);
@@ -357,9 +359,10 @@ te_status run_autotune(te_hamiltonian h, Workspace* w, hipStream_t s) {
     const int shapes[3][2] = {{4, 1}, {4, 4}, {8, 2}};
     double best_us = 1e30;
     hipError_t err = hipSuccess;
+    for (int sp = 0; sp <= 1 && err == hipSuccess; ++sp)
     for (int rp = 1; rp <= 2 && err == hipSuccess; ++rp) {
         for (const auto& sh : shapes) {
-            const Tiling t = make_tiling(w->dim, rp, sh[0], sh[1], rpt_u);
+            const Tiling t = make_tiling(w->dim, rp, sh[0], sh[1], rpt_u, sp);
             RedBuf rb = w->rb;
             rb.n_tiles = t.n_tiles_p;
             err = launch_project(t, h->csr, w->V, w->ld, J, w->y, w->st, rb, s);
@@ -373,7 +376,7 @@ te_status run_autotune(te_hamiltonian h, Workspace* w, hipStream_t s) {
             const double us = 1e3 * ms / 3.0;
             if (us < best_us) {
                 best_us = us;
-                best = te_tuning{sh[0], sh[1], rp, rpt_u, us};
+                best = te_tuning{sh[0], sh[1], rp, rpt_u, sp, us};
             }
         }
     }
@@ -686,14 +689,15 @@ te_status te_get_tuning(te_hamiltonian h, te_tuning* out) {
         *out = h->tuning;
     } else {
         const Tiling t = default_tiling(h->csr.dim);
-        *out = te_tuning{t.g, t.u, t.rpt_p, t.rpt_u, 0.0};
+        *out = te_tuning{t.g, t.u, t.rpt_p, t.rpt_u, t.split, 0.0};
     }
     return TE_OK;
 }
 
 te_status te_set_tuning(te_hamiltonian h, const te_tuning* t) {
     if (!h || !t) return fail(TE_ERR_INVALID_ARG, "null pointer");
-    if (!tiling_supported(t->rows_per_thread, t->lanes_per_row, t->nnz_per_lane, t->update_rows_per_thread))
+    if (!tiling_supported(t->rows_per_thread, t->lanes_per_row, t->nnz_per_lane, t->update_rows_per_thread,
+                          t->split_projection))
         return fail(TE_ERR_INVALID_ARG, "unsupported tuning (lanes 4 with 1 or 4 nonzeros, lanes 8 with 2; rows 1 or 2)");
     std::lock_guard<std::mutex> lock(h->mu);
     h->tuning = *t;

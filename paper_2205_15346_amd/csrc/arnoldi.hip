@@ -26,13 +26,14 @@ namespace te {
 
 int max_tiles(int dim) { return (dim + kBlock - 1) / kBlock; }
 
-bool tiling_supported(int rpt_p, int g, int u, int rpt_u) {
+bool tiling_supported(int rpt_p, int g, int u, int rpt_u, int split) {
     const bool shape = (g == 4 && (u == 1 || u == 4)) || (g == 8 && u == 2);
-    return shape && (rpt_p == 1 || rpt_p == 2) && (rpt_u == 1 || rpt_u == 2);
+    return shape && (rpt_p == 1 || rpt_p == 2) && (rpt_u == 1 || rpt_u == 2) && (split == 0 || split == 1);
 }
 
-Tiling make_tiling(int dim, int rpt_p, int g, int u, int rpt_u) {
+Tiling make_tiling(int dim, int rpt_p, int g, int u, int rpt_u, int split) {
     Tiling t;
+    t.split = split;
     t.rpt_p = rpt_p;
     t.g = g;
     t.u = u;
@@ -46,7 +47,7 @@ Tiling make_tiling(int dim, int rpt_p, int g, int u, int rpt_u) {
 // CU); measured on MI355X, 1-2 rows per thread stream at ~6.5 TB/s, 8 rows per thread at ~3.9.
 Tiling default_tiling(int dim) {
     const int rpt = ((int64_t)dim >= (int64_t)kBlock * 2 * 1024) ? 2 : 1;
-    return make_tiling(dim, rpt, 4, 4, rpt);
+    return make_tiling(dim, rpt, 4, 4, rpt, 0);
 }
 
 // ------------------------------------------------------------------- setup / copy
@@ -84,37 +85,119 @@ __global__ __launch_bounds__(kBlock) void k_copy(const double2* __restrict__ src
 }
 
 // -------------------------------------------------------------- project: SpMV + projections
-// Cross-lane reduction of 32 doubles per lane (8 columns x {Re, Im} x {y, x}): five halving
-// exchanges leave value (lane >> 1) in lanes 2q and 2q+1 after a last pairwise exchange;
-// 32 shuffles instead of 192 for independent butterflies.  Every index is a compile-time
-// constant so the array stays in registers.
-template <int H>
+// Cross-lane reduction of 32 doubles per lane (8 columns x {Re, Im} x {y, x}).  Five halving
+// steps: in each, a lane keeps one half of its values, sends the other half to a partner lane
+// and adds what the partner sent, so after step s each lane carries 32 / 2^s partial sums.
+// The partners are chosen so that four of the five exchanges are DPP lane permutations of a
+// plain VALU move (mirror within 16 lanes, mirror within 8, then the two quad swaps) and one
+// is an LDS swizzle (lane ^ 16 within 32); a last exchange across the halves of the wave
+// (lane ^ 32) completes the sums.  31 + 1 exchanges for 32 values instead of 6 per value for
+// independent butterflies.  A partner must hold the same value set: each permutation flips
+// the bit that decides which half a lane keeps and only bits not used by an earlier step.
+// Every index is a compile-time constant so the array stays in registers.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ __forceinline__ double swizzle_xor16(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_ds_swizzle((int)b, 0x401F);  // bitmask mode: and 31, xor 16
+    const int hi = __builtin_amdgcn_ds_swizzle((int)(b >> 32), 0x401F);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+constexpr int kDppRowMirror = 0x140;      // lane i <-> 15 - i within 16
+constexpr int kDppRowHalfMirror = 0x141;  // lane i <-> 7 - i within 8
+constexpr int kDppQuadXor2 = 0x4E;        // quad_perm [2, 3, 0, 1]
+constexpr int kDppQuadXor1 = 0xB1;        // quad_perm [1, 0, 3, 2]
+
+// H values move; BIT of the lane id decides which half is kept; EX selects the exchange
+template <int H, int BIT, int EX>
 __device__ __forceinline__ void halve(double (&a)[32], int lane) {
-    const bool hi = (lane & (2 * H)) != 0;
+    const bool hi = ((lane >> BIT) & 1) != 0;
 #pragma unroll
     for (int v = 0; v < H; ++v) {
         const double send = hi ? a[v] : a[v + H];
         const double keep = hi ? a[v + H] : a[v];
-        a[v] = keep + __shfl_xor(send, 2 * H);
+        double got;
+        if (EX == 0) got = dpp_move<kDppRowMirror>(send);
+        else if (EX == 1) got = dpp_move<kDppRowHalfMirror>(send);
+        else if (EX == 2) got = dpp_move<kDppQuadXor2>(send);
+        else if (EX == 3) got = dpp_move<kDppQuadXor1>(send);
+        else got = swizzle_xor16(send);
+        a[v] = keep + got;
     }
 }
 
+// Returns, in every lane, the full sum of value halving_value(lane & 31).
 __device__ __forceinline__ double halving_reduce32(double (&a)[32], int lane) {
-    halve<16>(a, lane);
-    halve<8>(a, lane);
-    halve<4>(a, lane);
-    halve<2>(a, lane);
-    halve<1>(a, lane);
-    return a[0] + __shfl_xor(a[0], 1);
+    halve<16, 3, 0>(a, lane);
+    halve<8, 2, 1>(a, lane);
+    halve<4, 1, 2>(a, lane);
+    halve<2, 0, 3>(a, lane);
+    halve<1, 4, 4>(a, lane);
+    return a[0] + __shfl_xor(a[0], 32);
 }
 
-template <int RPT, int G, int U>
+// index (0..31) of the value whose sum lanes l and l + 32 hold after halving_reduce32
+__device__ __forceinline__ int halving_value(int lane) {
+    return ((lane >> 3) & 1) * 16 + ((lane >> 2) & 1) * 8 + ((lane >> 1) & 1) * 4 + (lane & 1) * 2 + ((lane >> 4) & 1);
+}
+
+// y = H V[:, j] (raw) on rows [r0, r1): G lanes per row stream the CSR, each with U nonzeros
+// in flight; results to y and, if ytile is given, to LDS.
+template <int G, int U>
+__device__ __forceinline__ void tile_spmv(const int* __restrict__ rp, const int* __restrict__ ci,
+                                          const double2* __restrict__ val, const double2* __restrict__ x,
+                                          int r0, int r1, double2* __restrict__ y, double2* ytile) {
+    const int tid = threadIdx.x;
+    const int lg = tid % G, grp = tid / G;
+    for (int r = r0 + grp; r < r1; r += kBlock / G) {
+        double2 acc = make_double2(0.0, 0.0);
+        const int kb = rp[r], ke = rp[r + 1];
+        for (int k0 = kb + lg; k0 < ke; k0 += G * U) {
+            double2 vv[U];
+            int cc[U];
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                const int k = k0 + q * G;
+                if (k < ke) {
+                    vv[q] = val[k];
+                    cc[q] = ci[k];
+                } else {
+                    vv[q] = make_double2(0.0, 0.0);
+                    cc[q] = -1;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < U; ++q)
+                if (cc[q] >= 0) acc = cfma(vv[q], x[cc[q]], acc);
+        }
+#pragma unroll
+        for (int o = G / 2; o > 0; o >>= 1) {
+            acc.x += __shfl_xor(acc.x, o);
+            acc.y += __shfl_xor(acc.y, o);
+        }
+        if (lg == 0) {
+            y[r] = acc;
+            if (ytile) ytile[r - r0] = acc;
+        }
+    }
+}
+
+// Projection of iteration j on one tile.  FROM_Y: the sparse product already ran (k_yspmv)
+// and y is read back; otherwise it is computed here and kept in LDS.
+template <int RPT, int G, int U, bool FROM_Y>
 __device__ __forceinline__ void project_body(const int* __restrict__ rp, const int* __restrict__ ci,
                                              const double2* __restrict__ val, const double2* __restrict__ V,
                                              int64_t ld, int dim, int j, double2* __restrict__ y,
                                              const DevState* __restrict__ st, const RedBuf& rb, int tile) {
     constexpr int R = kBlock * RPT;
-    __shared__ double2 ytile[R];
+    __shared__ double2 ytile[FROM_Y ? 1 : R];
     __shared__ double2 wpart[kWaves][kMaxVals];
     if (st->done || j >= st->k_limit) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -122,49 +205,16 @@ __device__ __forceinline__ void project_body(const int* __restrict__ rp, const i
     const int r1 = min(r0 + R, dim);
     const double2* __restrict__ x = V + (int64_t)j * ld;
 
-    // y = H V[:, j] (raw): G lanes per row stream the CSR, each with U nonzeros in flight
-    {
-        const int lg = tid % G, grp = tid / G;
-        for (int r = r0 + grp; r < r1; r += kBlock / G) {
-            double2 acc = make_double2(0.0, 0.0);
-            const int kb = rp[r], ke = rp[r + 1];
-            for (int k0 = kb + lg; k0 < ke; k0 += G * U) {
-                double2 vv[U];
-                int cc[U];
-#pragma unroll
-                for (int q = 0; q < U; ++q) {
-                    const int k = k0 + q * G;
-                    if (k < ke) {
-                        vv[q] = val[k];
-                        cc[q] = ci[k];
-                    } else {
-                        vv[q] = make_double2(0.0, 0.0);
-                        cc[q] = -1;
-                    }
-                }
-#pragma unroll
-                for (int q = 0; q < U; ++q)
-                    if (cc[q] >= 0) acc = cfma(vv[q], x[cc[q]], acc);
-            }
-#pragma unroll
-            for (int o = G / 2; o > 0; o >>= 1) {
-                acc.x += __shfl_xor(acc.x, o);
-                acc.y += __shfl_xor(acc.y, o);
-            }
-            if (lg == 0) {
-                y[r] = acc;
-                ytile[r - r0] = acc;
-            }
-        }
+    if (!FROM_Y) {
+        tile_spmv<G, U>(rp, ci, val, x, r0, r1, y, ytile);
+        __syncthreads();
     }
-    __syncthreads();
-
     double2 yq[RPT], xq[RPT];
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
         const int r = r0 + tid + q * kBlock;
         if (r < r1) {
-            yq[q] = ytile[r - r0];
+            yq[q] = FROM_Y ? y[r] : ytile[r - r0];
             xq[q] = x[r];
         } else {
             yq[q] = make_double2(0.0, 0.0);
@@ -196,8 +246,8 @@ __device__ __forceinline__ void project_body(const int* __restrict__ rp, const i
             a[4 * b + 3] = cx.y;
         }
         const double s = halving_reduce32(a, lane);
-        if ((lane & 1) == 0) {
-            const int v = lane >> 1;  // 4 * column-in-batch + component
+        if (lane < 32) {
+            const int v = halving_value(lane);  // 4 * column-in-batch + component
             const int i = i0 + (v >> 2);
             if (i <= j) {
                 double* dst = (double*)&wpart[wave][2 * i + ((v >> 1) & 1)];
@@ -214,12 +264,23 @@ __device__ __forceinline__ void project_body(const int* __restrict__ rp, const i
     }
 }
 
-template <int RPT, int G, int U>
+template <int RPT, int G, int U, bool FROM_Y>
 __global__ __launch_bounds__(kBlock) void k_project(const int* __restrict__ rp, const int* __restrict__ ci,
                                                      const double2* __restrict__ val, const double2* __restrict__ V,
                                                      int64_t ld, int dim, int j, double2* __restrict__ y,
                                                      const DevState* __restrict__ st, RedBuf rb) {
-    project_body<RPT, G, U>(rp, ci, val, V, ld, dim, j, y, st, rb, blockIdx.x);
+    project_body<RPT, G, U, FROM_Y>(rp, ci, val, V, ld, dim, j, y, st, rb, blockIdx.x);
+}
+
+// sparse product alone (split projection): y = H V[:, j] on the rows of one projection tile
+template <int RPT, int G, int U>
+__global__ __launch_bounds__(kBlock) void k_yspmv(const int* __restrict__ rp, const int* __restrict__ ci,
+                                                   const double2* __restrict__ val, const double2* __restrict__ V,
+                                                   int64_t ld, int dim, int j, double2* __restrict__ y,
+                                                   const DevState* __restrict__ st) {
+    if (st->done || j >= st->k_limit) return;
+    const int r0 = blockIdx.x * kBlock * RPT;
+    tile_spmv<G, U>(rp, ci, val, V + (int64_t)j * ld, r0, min(r0 + kBlock * RPT, dim), y, nullptr);
 }
 
 // Batched projection.  Jobs that share H form a group; a group of one runs the fused kernel
@@ -331,8 +392,8 @@ __device__ __forceinline__ void tile_dots(const JobView& J, int j, int tile, dou
             a[4 * b + 3] = cx.y;
         }
         const double sum = halving_reduce32(a, lane);
-        if ((lane & 1) == 0) {
-            const int q = lane >> 1;
+        if (lane < 32) {
+            const int q = halving_value(lane);
             const int i = i0 + (q >> 2);
             if (i <= j) {
                 double* dst = (double*)&wpart[wave][2 * i + ((q >> 1) & 1)];
@@ -918,9 +979,17 @@ hipError_t launch_project(const Tiling& tl, const Csr& H, const double2* V, int6
     return by_rpt(tl.rpt_p, [&](auto r) {
         constexpr int RPT = decltype(r)::value;
         const dim3 grid(tl.n_tiles_p), block(kBlock);
-        if (tl.g == 8) k_project<RPT, 8, 2><<<grid, block, 0, s>>>(H.row_ptr, H.col, H.val, V, ld, H.dim, j, y, st, rb);
-        else if (tl.u == 1) k_project<RPT, 4, 1><<<grid, block, 0, s>>>(H.row_ptr, H.col, H.val, V, ld, H.dim, j, y, st, rb);
-        else k_project<RPT, 4, 4><<<grid, block, 0, s>>>(H.row_ptr, H.col, H.val, V, ld, H.dim, j, y, st, rb);
+        if (tl.split) {  // the sparse product keeps one row per thread; rpt_p shapes the projections
+            const dim3 g1((H.dim + kBlock - 1) / kBlock);
+            if (tl.g == 8) k_yspmv<1, 8, 2><<<g1, block, 0, s>>>(H.row_ptr, H.col, H.val, V, ld, H.dim, j, y, st);
+            else if (tl.u == 1) k_yspmv<1, 4, 1><<<g1, block, 0, s>>>(H.row_ptr, H.col, H.val, V, ld, H.dim, j, y, st);
+            else k_yspmv<1, 4, 4><<<g1, block, 0, s>>>(H.row_ptr, H.col, H.val, V, ld, H.dim, j, y, st);
+            k_project<RPT, 4, 4, true><<<grid, block, 0, s>>>(H.row_ptr, H.col, H.val, V, ld, H.dim, j, y, st, rb);
+        } else {
+            if (tl.g == 8) k_project<RPT, 8, 2, false><<<grid, block, 0, s>>>(H.row_ptr, H.col, H.val, V, ld, H.dim, j, y, st, rb);
+            else if (tl.u == 1) k_project<RPT, 4, 1, false><<<grid, block, 0, s>>>(H.row_ptr, H.col, H.val, V, ld, H.dim, j, y, st, rb);
+            else k_project<RPT, 4, 4, false><<<grid, block, 0, s>>>(H.row_ptr, H.col, H.val, V, ld, H.dim, j, y, st, rb);
+        }
     });
 }
 

@@ -156,7 +156,7 @@ struct te_engine_s {
     std::deque<te_job> queue;
     std::vector<te_job> resident;
     bool tuned = false;
-    te_tuning tuning{4, 4, 1, 0, 0.0};
+    te_tuning tuning{4, 4, 1, 0, 0, 0.0};
     te_profile prof{};
     double busy = 0.0, busy_since = -1.0;
     te_status err = TE_OK;
@@ -244,11 +244,11 @@ hipError_t enqueue_round(te_engine_s* e, const Plan& p, hipStream_t s, std::vect
     return r;
 }
 
-// Times every supported projection shape on plan p (iteration min(8, m-1)) and keeps the
+// Times every supported projection shape on plan p (iteration m/2) and keeps the
 // fastest.  Runs after the set-up of p's jobs and before their initial vectors are copied in:
 // it only writes the product vectors and partials, which the first round overwrites.
 te_status autotune(te_engine_s* e, const Plan& p) {
-    const int J = std::min(8, p.m - 1);
+    const int J = std::min(p.m / 2, p.m - 1);  // mid-restart: the mean cost over j = 0..m-1
     const int shapes[3][2] = {{4, 1}, {4, 4}, {8, 2}};
     hipEvent_t e0, e1;
     EHIP(hipEventCreate(&e0));

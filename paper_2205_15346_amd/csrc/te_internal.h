@@ -189,10 +189,11 @@ struct Tiling {
     int n_tiles_p;  // tiles (workgroups) of the projection kernel
     int rpt_u;      // rows per thread, update and recombination kernels (1 or 2)
     int n_tiles_u;
+    int split;      // 1: sparse product and projections as two launches (y read back)
 };
-Tiling make_tiling(int dim, int rpt_p, int g, int u, int rpt_u);
+Tiling make_tiling(int dim, int rpt_p, int g, int u, int rpt_u, int split);
 Tiling default_tiling(int dim);
-bool tiling_supported(int rpt_p, int g, int u, int rpt_u);
+bool tiling_supported(int rpt_p, int g, int u, int rpt_u, int split);
 int max_tiles(int dim);  // tiles of the finest tiling (rpt = 1): sizes the partial buffers
 
 hipError_t launch_setup(DevState* st, const Problem& prob, hipStream_t s);
@@ -255,7 +256,7 @@ struct te_hamiltonian_s {
     te::Workspace* ws = nullptr;
     te_profile prof{};
     bool tuned = false;  // tuning measured or set explicitly
-    te_tuning tuning{4, 4, 1, 1, 0.0};
+    te_tuning tuning{4, 4, 1, 1, 0, 0.0};
     ~te_hamiltonian_s();
 };
 

@@ -65,7 +65,7 @@ class te_profile(ctypes.Structure):
 class te_tuning(ctypes.Structure):
     _fields_ = [("lanes_per_row", ctypes.c_int32), ("nnz_per_lane", ctypes.c_int32),
                 ("rows_per_thread", ctypes.c_int32), ("update_rows_per_thread", ctypes.c_int32),
-                ("project_us", ctypes.c_double)]
+                ("split_projection", ctypes.c_int32), ("project_us", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -294,8 +294,9 @@ def te_get_tuning(H: Hamiltonian) -> te_tuning:
     return t
 
 
-def te_set_tuning(H: Hamiltonian, lanes_per_row, nnz_per_lane, rows_per_thread, update_rows_per_thread):
-    t = te_tuning(lanes_per_row, nnz_per_lane, rows_per_thread, update_rows_per_thread, 0.0)
+def te_set_tuning(H: Hamiltonian, lanes_per_row, nnz_per_lane, rows_per_thread, update_rows_per_thread,
+                  split_projection=0):
+    t = te_tuning(lanes_per_row, nnz_per_lane, rows_per_thread, update_rows_per_thread, split_projection, 0.0)
     _check(_lib.te_set_tuning(H.handle, ctypes.byref(t)))
 
 

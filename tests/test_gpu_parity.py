@@ -334,7 +334,8 @@ def test_error_paths():
 
 
 # ------------------------------------------------------------------- autotuned kernel shapes
-SHAPES = [(4, 1, 1, 1), (4, 4, 1, 1), (8, 2, 1, 1), (4, 1, 2, 2), (4, 4, 2, 2), (8, 2, 2, 2), (8, 2, 1, 2)]
+SHAPES = [(4, 1, 1, 1, 0), (4, 4, 1, 1, 0), (8, 2, 1, 1, 0), (4, 1, 2, 2, 0), (4, 4, 2, 2, 0), (8, 2, 2, 2, 0),
+          (8, 2, 1, 2, 0), (4, 4, 1, 1, 1), (8, 2, 2, 2, 1), (4, 1, 2, 1, 1)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
@@ -348,12 +349,31 @@ def test_every_kernel_shape_matches_oracle(shape):
         with hamiltonian(H) as h:
             te.te_set_tuning(h, *shape)
             got = te.te_get_tuning(h)
-            assert (got.lanes_per_row, got.nnz_per_lane, got.rows_per_thread, got.update_rows_per_thread) == shape
+            assert (got.lanes_per_row, got.nnz_per_lane, got.rows_per_thread, got.update_rows_per_thread,
+                    got.split_projection) == shape
             v, res = te.te_evolve(h, to_dev(v0), t, tol, m)
             v = to_host(v)
         ro = O.evolve(H, v0, t, tol, m)
         assert np.linalg.norm(v - ro.v) <= 2 * tol + 1e-12
         assert abs(res.steps - ro.steps) <= 1
+
+
+@pytest.mark.parametrize("shape", [(4, 4, 1, 1), (8, 2, 2, 2), (4, 1, 2, 1)])
+def test_split_projection_is_bitwise_the_fused_one(shape):
+    """Sparse product and projections as two launches (y read back from memory) accumulate in
+    the same order as the fused kernel: identical results."""
+    announce(f"split vs fused {shape}")
+    te = lib()
+    H, v0 = W.xxz_chain(13, seed=5)
+    out = []
+    with hamiltonian(H) as h:
+        x = to_dev(v0)
+        for split in (0, 1):
+            te.te_set_tuning(h, *shape, split)
+            v, res = te.te_evolve(h, x, 7.0, 1e-8, 40)
+            out.append((to_host(v), res.steps, res.err_bound))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert out[0][1:] == out[1][1:]
 
 
 def test_autotune_picks_a_supported_shape():
