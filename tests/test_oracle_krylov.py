@@ -218,8 +218,8 @@ def test_planted_wrong_residual_norm_is_caught(monkeypatch):
 def test_planted_superdiagonal_sign_is_caught(monkeypatch):
     good = O.krylov.arnoldi
 
-    def wrong(H, u, m, tol_rate):
-        ar = good(H, u, m, tol_rate)
+    def wrong(H, u, m, tol_rate, three_term=False):
+        ar = good(H, u, m, tol_rate, three_term)
         M = ar.M.copy()
         k = M.shape[0]
         M[np.arange(k - 1), np.arange(1, k)] *= -1.0      # M_{j,j+1} = +no instead of -no
@@ -231,8 +231,8 @@ def test_planted_superdiagonal_sign_is_caught(monkeypatch):
 def test_planted_missing_diagonal_is_caught(monkeypatch):
     good = O.krylov.arnoldi
 
-    def wrong(H, u, m, tol_rate):
-        ar = good(H, u, m, tol_rate)
+    def wrong(H, u, m, tol_rate, three_term=False):
+        ar = good(H, u, m, tol_rate, three_term)
         M = ar.M - np.diag(ar.M.diagonal())               # dropped M_jj term
         return O.ArnoldiResult(ar.V, M, ar.h, ar.k, ar.breakdown)
 
