@@ -94,6 +94,15 @@ typedef struct {
  * per-kernel durations and algorithmic bytes, read back with te_last_profile(). */
 #define TE_OPT_PROFILE 1u
 
+/* te_options.flags bit: build each Krylov basis with the three-term recurrence exactly as
+ * printed (eq. arnoldi / Alg. 1, step 1: subtract beta_{j-1} v_{j-1}, project on v_j, subtract)
+ * and no re-orthogonalisation against older vectors.  Moves 2 instead of j + 1 basis columns
+ * per pass (about 3x fewer bytes at m = 40).  The bound of eq. errorIntegral rests on the
+ * Arnoldi relation and a unit residual vector, which the recurrence keeps to rounding error,
+ * not on orthogonality; the basis loses orthogonality as j grows, so results differ from the
+ * default mode by up to the two bounds.  Also accepted by te_engine_config.opt. */
+#define TE_OPT_LANCZOS3 2u
+
 /* Kernel classes of one restart, in te_profile order. */
 enum {
     TE_KERNEL_PROJECT = 0, /* sparse product fused with all projections and the Gram column */
@@ -268,11 +277,12 @@ typedef struct {
     int32_t m;                      /* Krylov dimension, 2..TE_MAX_KRYLOV (clamped per job to dim) */
     int32_t max_jobs;               /* resident jobs at most, 1..16384 */
     uint64_t hbm_budget;            /* bytes of device memory for job workspaces, allocated once */
-    int32_t lanes_per_row;          /* projection shape: 4 or 8 lanes per row; 0 = autotune */
+    int32_t lanes_per_row;          /* sparse-product shape: 4 or 8 lanes per row; 0 = autotune */
     int32_t nnz_per_lane;           /* 1 or 4 with 4 lanes, 2 with 8 lanes */
-    int32_t update_rows_per_thread; /* 1 or 2; 0 = 2 if a resident dim >= 2^19, else 1 */
+    int32_t rows_per_thread;        /* projections: 1 or 2 rows per thread; 0 = 2 */
+    int32_t update_rows_per_thread; /* update and recombination: 1 or 2; 0 = 2 */
     uint32_t flags;                 /* TE_ENGINE_* */
-    te_options opt;                 /* step-size / quadrature options (opt.flags must be 0) */
+    te_options opt;                 /* step-size / quadrature options; opt.flags: 0 or TE_OPT_LANCZOS3 */
 } te_engine_config;
 
 enum { TE_JOB_QUEUED = 0, TE_JOB_RUNNING = 1, TE_JOB_DONE = 2, TE_JOB_FAILED = 3 };
@@ -300,8 +310,10 @@ typedef struct {
  * reduction partials); 0 for invalid arguments.  Host-only. */
 uint64_t te_job_footprint(int64_t dim, int32_t m);
 
-/* Fills the defaults: m=40, max_jobs=1024, hbm_budget=0 (must be set), autotuned shape,
- * threaded, te_default_options. */
+/* Fills the defaults: m=40, max_jobs=1024, hbm_budget=0 (must be set), autotuned sparse-product
+ * shape, 2 rows per thread, threaded, te_default_options.  A job's results are bitwise those of
+ * te_evolve with the same shape (te_set_tuning with the same lanes, nonzeros, rows per thread
+ * and update rows per thread). */
 void te_engine_default_config(te_engine_config* cfg);
 
 /* Allocates the pool (hbm_budget bytes) and the job slots on the current device.  stream:

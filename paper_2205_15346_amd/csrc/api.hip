@@ -219,7 +219,8 @@ size_t profile_events(int m) { return (size_t)(3 * m + 3); }
 
 // add one finished restart with Krylov dimension k to the profile.  A build that broke down
 // at k < m still ran the projection of iteration k (its fold detected the breakdown).
-hipError_t accumulate_profile(te_hamiltonian h, Workspace* w, std::vector<hipEvent_t>& E, int k, te_profile* p) {
+hipError_t accumulate_profile(te_hamiltonian h, Workspace* w, std::vector<hipEvent_t>& E, int k, bool three_term,
+                              te_profile* p) {
     const double d = (double)w->dim, nnz = (double)h->csr.nnz;
     auto span = [&](int a, int b, double* out) {
         float ms = 0.f;
@@ -234,8 +235,9 @@ hipError_t accumulate_profile(te_hamiltonian h, Workspace* w, std::vector<hipEve
         if (e != hipSuccess) return e;
         p->launches[TE_KERNEL_PROJECT] += 1;
         p->seconds[TE_KERNEL_PROJECT] += t;
-        // CSR (values, columns, row pointers), columns 0..j of V, y written
-        p->bytes[TE_KERNEL_PROJECT] += 20.0 * nnz + 4.0 * (d + 1) + 16.0 * d * (j + 2);
+        // CSR (values, columns, row pointers), columns i_lo..j of V, y written
+        const int cols = (three_term && j >= 1) ? 2 : j + 1;
+        p->bytes[TE_KERNEL_PROJECT] += 20.0 * nnz + 4.0 * (d + 1) + 16.0 * d * (cols + 1);
         e = span(3 * j + 1, 3 * j + 2, &t);
         if (e != hipSuccess) return e;
         p->launches[TE_KERNEL_FOLD] += 1;
@@ -245,8 +247,8 @@ hipError_t accumulate_profile(te_hamiltonian h, Workspace* w, std::vector<hipEve
         if (e != hipSuccess) return e;
         p->launches[TE_KERNEL_UPDATE] += 1;
         p->seconds[TE_KERNEL_UPDATE] += t;
-        // y and columns 0..j read, column j+1 written unless this is the last iteration
-        p->bytes[TE_KERNEL_UPDATE] += 16.0 * d * (j + 2) + ((j + 1 < w->m) ? 16.0 * d : 0.0);
+        // y and columns i_lo..j read, column j+1 written unless this is the last iteration
+        p->bytes[TE_KERNEL_UPDATE] += 16.0 * d * (cols + 1) + ((j + 1 < w->m) ? 16.0 * d : 0.0);
     }
     hipError_t e = span(3 * w->m, 3 * w->m + 1, &t);
     if (e != hipSuccess) return e;
@@ -429,13 +431,14 @@ Problem make_problem(const te_hamiltonian_s* h, const te_options& o, double t, d
     p.quad_max_level = o.quad_max_level;
     p.quad_min_level = o.quad_min_level;
     p.max_halvings = o.max_halvings;
+    p.three_term = (o.flags & TE_OPT_LANCZOS3) ? 1 : 0;
     return p;
 }
 
 te_status check_options(const te_options& o) {
     if (o.n_substeps < 1 || !(o.t_init > 0.0) || !std::isfinite(o.t_init) || !(o.shrink > 0.0) || !(o.shrink <= 1.0) ||
         !(o.quad_rel_tol > 0.0) || o.quad_max_level < 0 || o.quad_max_level > 20 || o.quad_min_level < 0 ||
-        o.max_halvings < 0 || (o.flags & ~TE_OPT_PROFILE) != 0)
+        o.max_halvings < 0 || (o.flags & ~(TE_OPT_PROFILE | TE_OPT_LANCZOS3)) != 0)
         return fail(TE_ERR_INVALID_ARG, "invalid te_options");
     return TE_OK;
 }
@@ -618,14 +621,14 @@ te_status te_evolve(te_hamiltonian h, const te_c128* v0, te_c128* v_out, double 
         TE_HIP(hipEventRecord(w->ev[r & 1], s));
         if (r >= 1) {
             TE_HIP(hipEventSynchronize(w->ev[(r - 1) & 1]));
-            if (profile && r - 1 < flag[1]) TE_HIP(accumulate_profile(h, w, w->pev[(r - 1) & 1], flag[8 + ((r - 1) & 7)], &h->prof));
+            if (profile && r - 1 < flag[1]) TE_HIP(accumulate_profile(h, w, w->pev[(r - 1) & 1], flag[8 + ((r - 1) & 7)], prob.three_term != 0, &h->prof));
             if (flag[0]) break;
         }
         if (r >= max_restarts) return fail(TE_ERR_DEVICE, "restart limit reached");
     }
     if (profile) {
         TE_HIP(hipEventSynchronize(w->ev[r & 1]));
-        if (r < flag[1]) TE_HIP(accumulate_profile(h, w, w->pev[r & 1], flag[8 + (r & 7)], &h->prof));
+        if (r < flag[1]) TE_HIP(accumulate_profile(h, w, w->pev[r & 1], flag[8 + (r & 7)], prob.three_term != 0, &h->prof));
     }
     TE_HIP(launch_output(w->V, (double2*)v_out, dim, w->st, s));
     DevState hs;

@@ -33,7 +33,7 @@ namespace {
 
 constexpr int kRing = 4;        // round events in the ring
 constexpr int kDepth = 2;       // rounds on the device at once (one queued behind the running one)
-constexpr int kTileRows = kBlock;  // rows per tile of the grouped projection
+constexpr int kTileRows = kBlock;  // rows per tile of the multi-vector product
 constexpr int kMaxEngineJobs = 16384;
 const int kClasses[4] = {1, 2, 4, 8};
 
@@ -156,7 +156,7 @@ struct te_engine_s {
     std::deque<te_job> queue;
     std::vector<te_job> resident;
     bool tuned = false;
-    te_tuning tuning{4, 4, 1, 0, 0, 0.0};
+    te_tuning tuning{4, 4, 2, 2, 0, 0.0};
     te_profile prof{};
     double busy = 0.0, busy_since = -1.0;
     te_status err = TE_OK;
@@ -201,7 +201,7 @@ JobView job_view(te_engine_s* e, const JobRec& j, int rpt_u) {
     v.rb.part = (double2*)(base + L.part);
     v.rb.npart = (double*)(base + L.npart);
     v.rb.red = (double2*)(base + L.red);
-    v.rb.n_tiles = (int)ceil_div(j.dim, kTileRows);
+    v.rb.n_tiles = (int)ceil_div(j.dim, (int64_t)kBlock * e->tuning.rows_per_thread);
     v.rb.n_norm = (int)ceil_div(j.dim, (int64_t)kBlock * rpt_u);
     v.v0 = j.v0;
     v.out = j.out;
@@ -225,9 +225,9 @@ hipError_t enqueue_round(te_engine_s* e, const Plan& p, hipStream_t s, std::vect
     mark(0);
     for (int j = 0; j < p.m && r == hipSuccess; ++j) {
         for (int c = 0; c < 4 && r == hipSuccess; ++c)
-            r = launch_gproject(t.lanes_per_row, t.nnz_per_lane, kClasses[c], p.jobs, p.groups, p.pitems[c],
-                                p.n_pitems[c], j, s);
-        if (r == hipSuccess) r = launch_bdots(p.jobs, p.ditems, p.n_ditems, j, s);
+            r = launch_gproject(t.lanes_per_row, t.nnz_per_lane, t.rows_per_thread, kClasses[c], p.jobs, p.groups,
+                                p.pitems[c], p.n_pitems[c], j, s);
+        if (r == hipSuccess) r = launch_bdots(t.rows_per_thread, p.jobs, p.ditems, p.n_ditems, j, s);
         mark(3 * j + 1);
         if (r == hipSuccess) r = launch_bfold(p.jobs, p.n_jobs, j, s);
         mark(3 * j + 2);
@@ -259,9 +259,9 @@ te_status autotune(te_engine_s* e, const Plan& p) {
     for (const auto& sh : shapes) {
         auto launch_all = [&]() {
             for (int c = 0; c < 4 && r == hipSuccess; ++c)
-                r = launch_gproject(sh[0], sh[1], kClasses[c], p.jobs, p.groups, p.pitems[c], p.n_pitems[c], J,
-                                    e->stream);
-            if (r == hipSuccess) r = launch_bdots(p.jobs, p.ditems, p.n_ditems, J, e->stream);
+                r = launch_gproject(sh[0], sh[1], e->tuning.rows_per_thread, kClasses[c], p.jobs, p.groups,
+                                    p.pitems[c], p.n_pitems[c], J, e->stream);
+            if (r == hipSuccess) r = launch_bdots(e->tuning.rows_per_thread, p.jobs, p.ditems, p.n_ditems, J, e->stream);
         };
         launch_all();
         if (r == hipSuccess) r = hipEventRecord(e0, e->stream);
@@ -347,9 +347,9 @@ te_status build_plan(te_engine_s* e) {
     });
     int max_dim = 0;
     for (te_job id : ids) max_dim = std::max(max_dim, e->jobs[(size_t)id].dim);
-    int rpt_u = e->cfg.update_rows_per_thread;
-    if (rpt_u == 0) rpt_u = (max_dim >= (1 << 19)) ? 2 : 1;
-    e->tuning.update_rows_per_thread = rpt_u;
+    const int rpt_u = e->tuning.update_rows_per_thread;
+    const int rpt_p = e->tuning.rows_per_thread;
+    (void)max_dim;
 
     p.job_ids = ids;
     p.group_jobs.clear();
@@ -372,9 +372,13 @@ te_status build_plan(te_engine_s* e) {
     int64_t n_items_c[4] = {0, 0, 0, 0}, n_u = 0, n_new_items = 0, n_d = 0;
     for (const auto& g : p.group_jobs) {
         const JobRec& j0 = e->jobs[(size_t)ids[(size_t)g[0]]];
-        const int64_t tiles = ceil_div(j0.dim, kTileRows);
-        n_items_c[nv_class_index((int)g.size())] += tiles;
-        if (g.size() > 1) n_d += tiles * (int64_t)g.size();
+        const int64_t ptiles = ceil_div(j0.dim, (int64_t)kBlock * rpt_p);  // projection tiles
+        if (g.size() == 1) {
+            n_items_c[0] += ptiles;
+        } else {
+            n_items_c[nv_class_index((int)g.size())] += ceil_div(j0.dim, kTileRows);
+            n_d += ptiles * (int64_t)g.size();
+        }
     }
     for (te_job id : ids) {
         const JobRec& j = e->jobs[(size_t)id];
@@ -436,11 +440,15 @@ te_status build_plan(te_engine_s* e) {
         for (int q = 0; q < kMaxGroup; ++q) gv.job[q] = q < gv.nv ? g[(size_t)q] : 0;
         hg[gi] = gv;
         const int c = nv_class_index(gv.nv);
-        const int tiles = (int)ceil_div(j0.dim, kTileRows);
-        for (int t = 0; t < tiles; ++t) hp[c][fill_c[c]++] = make_int2(gi, t);
-        if (gv.nv > 1)
-            for (int t = 0; t < tiles; ++t)
+        const int ptiles = (int)ceil_div(j0.dim, (int64_t)kBlock * rpt_p);
+        if (gv.nv == 1) {
+            for (int t = 0; t < ptiles; ++t) hp[0][fill_c[0]++] = make_int2(gi, t);
+        } else {
+            const int tiles = (int)ceil_div(j0.dim, kTileRows);
+            for (int t = 0; t < tiles; ++t) hp[c][fill_c[c]++] = make_int2(gi, t);
+            for (int t = 0; t < ptiles; ++t)
                 for (int q = 0; q < gv.nv; ++q) hd[fill_d++] = make_int2(g[(size_t)q], t);
+        }
     }
     int fu = 0, fn = 0, fni = 0;
     for (int i = 0; i < p.n_jobs; ++i) {
@@ -504,6 +512,7 @@ te_status build_plan(te_engine_s* e) {
 // algorithmic bytes of one round of plan p for the jobs whose restart in that round had
 // Krylov dimension k (k = 0: the job did not run); per kernel class as in te_evolve
 void round_bytes(const te_engine_s* e, const Plan& p, const std::vector<int>& kk, te_profile* pr) {
+    const bool three = (e->cfg.opt.flags & TE_OPT_LANCZOS3) != 0;
     for (const auto& g : p.group_jobs) {
         const JobRec& j0 = e->jobs[(size_t)p.job_ids[(size_t)g[0]]];
         const double d = (double)j0.dim, nnz = (double)j0.h->csr.nnz;
@@ -513,11 +522,12 @@ void round_bytes(const te_engine_s* e, const Plan& p, const std::vector<int>& kk
                 const int k = kk[(size_t)q];
                 const int m = e->jobs[(size_t)p.job_ids[(size_t)q]].m;
                 if (k <= 0) continue;
+                const int cols = (three && j >= 1) ? 2 : j + 1;  // basis columns the iteration reads
                 if (j < std::min(k + 1, m)) {
                     any = true;
-                    pr->bytes[TE_KERNEL_PROJECT] += 16.0 * d * (j + 2);
+                    pr->bytes[TE_KERNEL_PROJECT] += 16.0 * d * (cols + 1);
                 }
-                if (j < k) pr->bytes[TE_KERNEL_UPDATE] += 16.0 * d * (j + 2) + ((j + 1 < m) ? 16.0 * d : 0.0);
+                if (j < k) pr->bytes[TE_KERNEL_UPDATE] += 16.0 * d * (cols + 1) + ((j + 1 < m) ? 16.0 * d : 0.0);
             }
             if (any) pr->bytes[TE_KERNEL_PROJECT] += 20.0 * nnz + 4.0 * (d + 1);
         }
@@ -721,10 +731,12 @@ te_status check_config(const te_engine_config& c) {
     if (c.max_jobs < 1 || c.max_jobs > kMaxEngineJobs) return set_error(TE_ERR_INVALID_ARG, "max_jobs out of range");
     if (c.lanes_per_row != 0 && !gproject_supported(c.lanes_per_row, c.nnz_per_lane))
         return set_error(TE_ERR_INVALID_ARG, "unsupported projection shape (4 lanes with 1 or 4 nonzeros, 8 with 2)");
-    if (c.update_rows_per_thread < 0 || c.update_rows_per_thread > 2)
-        return set_error(TE_ERR_INVALID_ARG, "update_rows_per_thread must be 0, 1 or 2");
+    if (c.update_rows_per_thread < 0 || c.update_rows_per_thread > 2 || c.rows_per_thread < 0 ||
+        c.rows_per_thread > 2)
+        return set_error(TE_ERR_INVALID_ARG, "rows_per_thread and update_rows_per_thread must be 0, 1 or 2");
     if (c.flags & ~(TE_ENGINE_THREADED | TE_ENGINE_PROFILE)) return set_error(TE_ERR_INVALID_ARG, "unknown flags");
-    if (c.opt.flags != 0) return set_error(TE_ERR_INVALID_ARG, "engine options take no flags");
+    if (c.opt.flags & ~TE_OPT_LANCZOS3)
+        return set_error(TE_ERR_INVALID_ARG, "engine options take only TE_OPT_LANCZOS3 (profiling: TE_ENGINE_PROFILE)");
     return check_options(c.opt);
 }
 
@@ -765,6 +777,7 @@ void te_engine_default_config(te_engine_config* c) {
     c->hbm_budget = 0;
     c->lanes_per_row = 0;
     c->nnz_per_lane = 0;
+    c->rows_per_thread = 0;
     c->update_rows_per_thread = 0;
     c->flags = TE_ENGINE_THREADED;
     te_default_options(&c->opt);
@@ -784,7 +797,8 @@ te_status te_engine_create(te_engine* out, const te_engine_config* cfg, void* st
         e->tuning.nnz_per_lane = cfg->nnz_per_lane;
         e->tuned = true;
     }
-    e->tuning.rows_per_thread = 1;
+    e->tuning.rows_per_thread = cfg->rows_per_thread ? cfg->rows_per_thread : 2;
+    e->tuning.update_rows_per_thread = cfg->update_rows_per_thread ? cfg->update_rows_per_thread : 2;
     auto chk = [&](hipError_t r, const char* what) {
         if (r != hipSuccess && rc == TE_OK) rc = hip_fail(r, what);
     };

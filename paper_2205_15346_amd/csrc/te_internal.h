@@ -28,6 +28,8 @@ struct Problem {
     double t_init, shrink, quad_rel_tol;
     int32_t m, dim;
     int32_t n_substeps, quad_max_level, quad_min_level, max_halvings;
+    int32_t three_term;  // Krylov step: 0 full re-orthogonalisation, 1 three-term recurrence only
+    int32_t pad_;
 };
 
 struct DevState {
@@ -76,7 +78,7 @@ struct JobView {
     double2* V;          // basis columns, leading dimension ld
     double2* y;          // raw product H V[:, j]
     DevState* st;
-    RedBuf rb;           // n_tiles = tiles of the grouped projection (256 rows each)
+    RedBuf rb;           // n_tiles = projection tiles (kBlock * rows per thread rows each)
     const double2* v0;   // caller's initial vector (read at admission)
     double2* out;        // caller's output vector (written when the job completes)
     int64_t ld;
@@ -215,9 +217,9 @@ hipError_t launch_validate(const Csr& H, int check_hermitian, int* err, double* 
 hipError_t launch_norm1(const double* rowsum, int dim, double* out, hipStream_t s);
 
 // batched launchers: items are (group or job, tile) pairs, one workgroup each
-hipError_t launch_gproject(int g, int u, int nv_class, const JobView* jobs, const GroupView* groups,
+hipError_t launch_gproject(int g, int u, int rpt, int nv_class, const JobView* jobs, const GroupView* groups,
                            const int2* items, int n_items, int j, hipStream_t s);
-hipError_t launch_bdots(const JobView* jobs, const int2* items, int n_items, int j, hipStream_t s);
+hipError_t launch_bdots(int rpt, const JobView* jobs, const int2* items, int n_items, int j, hipStream_t s);
 hipError_t launch_bfold(const JobView* jobs, int n_jobs, int j, hipStream_t s);
 hipError_t launch_bupdate(int rpt, const JobView* jobs, const int2* items, int n_items, int j, hipStream_t s);
 hipError_t launch_bstep(const JobView* jobs, int n_jobs, hipStream_t s);

@@ -51,6 +51,7 @@ class te_result(ctypes.Structure):
 
 
 TE_OPT_PROFILE = 1
+TE_OPT_LANCZOS3 = 2
 KERNEL_CLASSES = ("project", "update", "step", "combine", "fold")
 
 
@@ -80,7 +81,8 @@ JOB_STATES = ("queued", "running", "done", "failed")
 class te_engine_config(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int32), ("max_jobs", ctypes.c_int32), ("hbm_budget", ctypes.c_uint64),
                 ("lanes_per_row", ctypes.c_int32), ("nnz_per_lane", ctypes.c_int32),
-                ("update_rows_per_thread", ctypes.c_int32), ("flags", ctypes.c_uint32), ("opt", te_options)]
+                ("rows_per_thread", ctypes.c_int32), ("update_rows_per_thread", ctypes.c_int32),
+                ("flags", ctypes.c_uint32), ("opt", te_options)]
 
 
 class te_job_info(ctypes.Structure):
@@ -385,13 +387,14 @@ def te_engine_default_config(**overrides) -> te_engine_config:
     return c
 
 
-def _engine_config(m, max_jobs, hbm_budget, shape, update_rows_per_thread, flags, options):
+def _engine_config(m, max_jobs, hbm_budget, shape, update_rows_per_thread, flags, options, rows_per_thread=0):
     c = te_engine_default_config()
     c.m = int(m)
     c.max_jobs = int(max_jobs)
     c.hbm_budget = int(hbm_budget)
     if shape is not None:
         c.lanes_per_row, c.nnz_per_lane = int(shape[0]), int(shape[1])
+    c.rows_per_thread = int(rows_per_thread)
     c.update_rows_per_thread = int(update_rows_per_thread)
     c.flags = int(flags)
     if options is not None:
@@ -404,9 +407,10 @@ class Engine:
     until it is done; `submit` returns the job id."""
 
     def __init__(self, hbm_budget, m=40, max_jobs=1024, shape=None, update_rows_per_thread=0, threaded=True,
-                 profile=False, options=None, stream=None):
+                 profile=False, options=None, stream=None, rows_per_thread=0):
         flags = (TE_ENGINE_THREADED if threaded else 0) | (TE_ENGINE_PROFILE if profile else 0)
-        cfg = _engine_config(m, max_jobs, hbm_budget, shape, update_rows_per_thread, flags, options)
+        cfg = _engine_config(m, max_jobs, hbm_budget, shape, update_rows_per_thread, flags, options,
+                             rows_per_thread)
         self._e = _P()
         st = ctypes.c_void_p(0) if stream is None else _stream(stream)
         _check(_lib.te_engine_create(ctypes.byref(self._e), ctypes.byref(cfg), st))
@@ -459,13 +463,13 @@ class Engine:
 
 
 def te_batch_run(groups, m=40, hbm_budget=0, max_jobs=0, shape=None, update_rows_per_thread=0, profile=False,
-                 options=None, stream=None):
+                 options=None, stream=None, rows_per_thread=0):
     """te_batch_create / add / launch / result / info / destroy over `groups`, a list of
     (Hamiltonian, [v0 tensors], t, tol).  Returns (outputs per group, [(te_result, status,
     te_job_info)] in submission order, te_engine_stats)."""
     import torch
     flags = TE_ENGINE_PROFILE if profile else 0
-    cfg = _engine_config(m, max_jobs, 0, shape, update_rows_per_thread, flags, options)
+    cfg = _engine_config(m, max_jobs, 0, shape, update_rows_per_thread, flags, options, rows_per_thread)
     b = _P()
     st = ctypes.c_void_p(0) if stream is None else _stream(stream)
     _check(_lib.te_batch_create(ctypes.byref(b), ctypes.byref(cfg), st))

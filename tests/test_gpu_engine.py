@@ -19,12 +19,13 @@ from tests.gpu_util import announce, hamiltonian, lib, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 SHAPE = (4, 4)
+TUNE = dict(shape=SHAPE, rows_per_thread=2, update_rows_per_thread=2)
 M = 40
 
 
-def alone(h, v0, t, tol, shape=SHAPE, rpt_u=1, m=M):
+def alone(h, v0, t, tol, shape=SHAPE, rpt=2, rpt_u=2, m=M, split=0):
     te = lib()
-    te.te_set_tuning(h, shape[0], shape[1], 1, rpt_u)
+    te.te_set_tuning(h, shape[0], shape[1], rpt, rpt_u, split)
     out, res = te.te_evolve(h, v0, t, tol, m)
     return out.clone(), res
 
@@ -51,20 +52,22 @@ def mixed_groups():
     return groups
 
 
-def test_batch_bitwise_equals_alone(mixed_groups):
+@pytest.mark.parametrize("tune", [((4, 4), 2, 2), ((8, 2), 1, 1), ((4, 1), 2, 1)])
+def test_batch_bitwise_equals_alone(mixed_groups, tune):
     te = lib()
+    shape, rpt, rpt_u = tune
     hs = [hamiltonian(H) for H, _, _, _ in mixed_groups]
     dev = [[to_dev(v) for v in vs] for _, vs, _, _ in mixed_groups]
-    announce("batch of 9 jobs on 5 Hamiltonians, shape (4,4)")
+    announce(f"batch of 9 jobs on 5 Hamiltonians, shape {tune}")
     outs, results, stats = te.te_batch_run([(h, d, t, tol) for h, d, (_, _, t, tol) in zip(hs, dev, mixed_groups)],
-                                           m=M, shape=SHAPE, update_rows_per_thread=1)
+                                           m=M, shape=shape, rows_per_thread=rpt, update_rows_per_thread=rpt_u)
     assert stats.jobs_done == 9 and stats.jobs_failed == 0
     assert stats.rounds >= max(r.steps for r, _, _ in results)
     i = 0
     for gi, (h, d, (_, _, t, tol)) in enumerate(zip(hs, dev, mixed_groups)):
         for vi, v in enumerate(d):
             announce(f"alone: group {gi} vector {vi}")
-            ref, rres = alone(h, v, t, tol)
+            ref, rres = alone(h, v, t, tol, shape=shape, rpt=rpt, rpt_u=rpt_u, split=vi % 2)
             res, status, _ = results[i]
             assert status == te.TE_OK
             assert same_result(res, rres), (gi, vi, res.as_dict(), rres.as_dict())
@@ -99,7 +102,7 @@ def test_batch_autotuned_agrees_with_alone(mixed_groups):
     i = 0
     for gi, (h, d, (_, _, t, tol)) in enumerate(zip(hs, dev, mixed_groups)):
         for vi, v in enumerate(d):
-            ref, rres = alone(h, v, t, tol, shape=(8, 2), rpt_u=2)
+            ref, rres = alone(h, v, t, tol, shape=(8, 2), rpt=1, rpt_u=1)
             res, status, _ = results[i]
             assert status == te.TE_OK
             err = float((outs[gi][vi] - ref).norm())
@@ -123,7 +126,7 @@ def test_engine_alone_and_in_the_mix():
                 ("A2", hA, vA[0], 20.0, 1e-8), ("E", hA, vA[2], 5.0, 1e-8)]
         dev = {name: to_dev(v) for name, _, v, _, _ in reqs}
         dev["A"] = dev["A2"]
-        with te.Engine(budget, m=M, max_jobs=8, shape=SHAPE, update_rows_per_thread=1) as eng:
+        with te.Engine(budget, m=M, max_jobs=8, **TUNE) as eng:
             announce("engine: A alone")
             ja = eng.submit(hA, dev["A"], 20.0, 1e-8)
             eng.wait(ja, timeout=120)
@@ -163,7 +166,7 @@ def test_engine_admission_by_footprint():
     budget = int(2.5 * fp)
     with hamiltonian(H) as h:
         dev = [to_dev(v) for v in vs]
-        with te.Engine(budget, m=M, max_jobs=16, shape=SHAPE, update_rows_per_thread=1) as eng:
+        with te.Engine(budget, m=M, max_jobs=16, **TUNE) as eng:
             announce("engine: 5 jobs, budget for 2")
             ids = [eng.submit(h, d, 10.0, 1e-8) for d in dev]
             eng.wait(-1, timeout=300)
@@ -196,8 +199,7 @@ def test_engine_edge_cases_do_not_disturb_the_mix():
         zero = torch.zeros_like(good)
         bad = to_dev(vs[1])
         bad[7] = complex(float("nan"), 0.0)
-        with te.Engine(8 * te.te_job_footprint(1024, M), m=M, max_jobs=8, shape=SHAPE, update_rows_per_thread=1,
-                       threaded=False) as eng:
+        with te.Engine(8 * te.te_job_footprint(1024, M), m=M, max_jobs=8, threaded=False, **TUNE) as eng:
             announce("engine: t=0, zero v0, NaN v0 next to a normal job")
             j0 = eng.submit(h, good, 0.0, 1e-8)
             jz = eng.submit(h, zero, 5.0, 1e-8)
@@ -223,9 +225,8 @@ def test_engine_profile_mode_accounts_every_kernel_class(mixed_groups):
     with hamiltonian(H) as h:
         d = [to_dev(v) for v in vs]
         announce("batch in profiling mode")
-        outs_p, res_p, st = te.te_batch_run([(h, d, t, tol)], m=M, shape=SHAPE, update_rows_per_thread=1,
-                                            profile=True)
-        outs_g, res_g, _ = te.te_batch_run([(h, d, t, tol)], m=M, shape=SHAPE, update_rows_per_thread=1)
+        outs_p, res_p, st = te.te_batch_run([(h, d, t, tol)], m=M, profile=True, **TUNE)
+        outs_g, res_g, _ = te.te_batch_run([(h, d, t, tol)], m=M, **TUNE)
         for a, b in zip(outs_p[0], outs_g[0]):
             assert bool((a == b).all())
         prof = st.prof.as_dict()
@@ -249,7 +250,7 @@ def test_batch_sample_of_the_256_instance_workload():
         host.append((H, vs))
         groups.append((h, [to_dev(v) for v in vs], j.t, j.tol))
     announce(f"batch sample: L={[j.L for j in jobs]} n_v0={[j.n_v0 for j in jobs]}")
-    outs, results, stats = te.te_batch_run(groups, m=M, shape=SHAPE, update_rows_per_thread=1)
+    outs, results, stats = te.te_batch_run(groups, m=M, **TUNE)
     assert stats.jobs_done == sum(j.n_v0 for j in jobs)
     k = 0
     for gi, (h, d, t, tol) in enumerate(groups):
