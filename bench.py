@@ -82,6 +82,32 @@ def kernel_rates(prof):
             for k, v in prof.items()}
 
 
+def bench_three_term(te, torch, H, v0, out, wl, steps):
+    """The headline solve with TE_OPT_LANCZOS3 (three-term recurrence, no re-orthogonalisation)."""
+    o3 = te.te_default_options(flags=te.TE_OPT_PROFILE | te.TE_OPT_LANCZOS3)
+    te.te_evolve(H, v0, wl.t, wl.tol, wl.m, options=o3, out=out)
+    t3 = {k: {"seconds": 0.0, "bytes": 0.0} for k in te.KERNEL_CLASSES}
+    torch.cuda.synchronize()
+    s0 = time.perf_counter()
+    for i in range(steps):
+        _, res3 = te.te_evolve(H, v0, wl.t, wl.tol, wl.m, options=o3, out=out)
+        p = te.te_last_profile(H).as_dict()
+        for k in t3:
+            t3[k]["seconds"] += p[k]["seconds"]
+            t3[k]["bytes"] += p[k]["bytes"]
+    torch.cuda.synchronize()
+    e3 = time.perf_counter() - s0
+    log(f"[bench] three-term mode: {1e3 * e3 / steps:.1f} ms per solve, restarts={res3.steps}, "
+        f"bound={res3.err_bound:.3e}")
+    return {
+        "value": steps / e3, "ms_per_step": 1e3 * e3 / steps, "restarts_per_solve": res3.steps,
+        "err_bound": res3.err_bound,
+        "kernel_gbs": {k: (v["bytes"] / v["seconds"] / 1e9 if v["seconds"] > 0 and v["bytes"] > 0 else None)
+                       for k, v in t3.items()},
+        "kernel_ms_per_solve": {k: 1e3 * v["seconds"] / steps for k, v in t3.items()},
+    }
+
+
 def bench_batch(te, torch, dev, n_instances, m, profile):
     """The 256-instance XXZ batch (L ~ U{10..18}, 1-8 vectors each, t ~ U[1,100], tol in
     {1e-6, 1e-8, 1e-10}) through te_batch_*, against the same jobs one at a time through
@@ -237,6 +263,7 @@ def main():
     ap.add_argument("--shape", default="8,2,2,2,1",
                     help="projection kernel shape lanes,nnz,rows,update_rows,split for the single solve "
                          "(default: the shape te_autotune selects for this matrix on MI355X), or 'auto'")
+    ap.add_argument("--three-term", type=int, default=1, help="also time the three-term mode (0: skip)")
     ap.add_argument("--batch-instances", type=int, default=256, help="instances of the XXZ batch (0: skip)")
     ap.add_argument("--batch-profile", type=int, default=1, help="also run the batch in profiling mode")
     ap.add_argument("--serve-requests", type=int, default=16, help="requests of the serving run (0: skip)")
@@ -300,28 +327,7 @@ def main():
     graph_elapsed = time.perf_counter() - g0
 
     # ---- three-term mode (TE_OPT_LANCZOS3; informational, not the headline)
-    o3 = te.te_default_options(flags=te.TE_OPT_PROFILE | te.TE_OPT_LANCZOS3)
-    te.te_evolve(H, v0, wl.t, wl.tol, wl.m, options=o3, out=out)
-    t3 = {k: {"seconds": 0.0, "bytes": 0.0} for k in te.KERNEL_CLASSES}
-    torch.cuda.synchronize()
-    s0 = time.perf_counter()
-    for i in range(args.steps):
-        _, res3 = te.te_evolve(H, v0, wl.t, wl.tol, wl.m, options=o3, out=out)
-        p = te.te_last_profile(H).as_dict()
-        for k in t3:
-            t3[k]["seconds"] += p[k]["seconds"]
-            t3[k]["bytes"] += p[k]["bytes"]
-    torch.cuda.synchronize()
-    e3 = time.perf_counter() - s0
-    three_term = {
-        "value": args.steps / e3, "ms_per_step": 1e3 * e3 / args.steps, "restarts_per_solve": res3.steps,
-        "err_bound": res3.err_bound,
-        "kernel_gbs": {k: (v["bytes"] / v["seconds"] / 1e9 if v["seconds"] > 0 and v["bytes"] > 0 else None)
-                       for k, v in t3.items()},
-        "kernel_ms_per_solve": {k: 1e3 * v["seconds"] / args.steps for k, v in t3.items()},
-    }
-    log(f"[bench] three-term mode: {1e3 * e3 / args.steps:.1f} ms per solve, restarts={res3.steps}, "
-        f"bound={res3.err_bound:.3e}")
+    three_term = bench_three_term(te, torch, H, v0, out, wl, args.steps) if args.three_term else None
 
     kernel_gbs = {k: (v["bytes"] / v["seconds"] / 1e9 if v["seconds"] > 0 else None) for k, v in totals.items()}
     traffic = measured_traffic(os.path.join(ROOT, "paper_2205_15346_amd", "csrc", "arnoldi.hip"))
@@ -376,6 +382,13 @@ def main():
         },
         "cpu_baseline": {k: v for k, v in cpu.items() if k != "seconds_per_solve"} if cpu else None,
         "hbm_gbs_algorithmic_all_kernels": alg_bytes / kernel_seconds / 1e9,
+        "spmv_orthogonalisation": {
+            "kernels": ["project", "fold", "update"],
+            "gbs": sum(totals[k]["bytes"] for k in ("project", "fold", "update"))
+            / sum(totals[k]["seconds"] for k in ("project", "fold", "update")) / 1e9,
+            "frac_of_peak": sum(totals[k]["bytes"] for k in ("project", "fold", "update"))
+            / sum(totals[k]["seconds"] for k in ("project", "fold", "update")) / 1e9 / HBM_PEAK_GBS,
+        },
         "hbm_gbs_algorithmic_wall": alg_bytes / elapsed / 1e9,
         "kernel_gbs": kernel_gbs,
         "kernel_ms_per_solve": {k: 1e3 * v["seconds"] / args.steps for k, v in totals.items()},
