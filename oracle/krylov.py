@@ -94,6 +94,8 @@ class EvolveResult:
     breakdown_dim: int
     t_reached: float
     trace: List[StepRecord] = field(default_factory=list)
+    samples: Optional[np.ndarray] = None        # [n_times, d]: states at the sample times
+    sample_bounds: Optional[np.ndarray] = None  # bound at the end of the step holding each time
 
 
 def spmv(H, x: np.ndarray) -> np.ndarray:
@@ -234,12 +236,15 @@ def krylov_coefficients(lam: np.ndarray, U: np.ndarray, tau: float) -> np.ndarra
 
 def evolve(H, v0: np.ndarray, t: float, tol: float, m: int, opts: Optional[Options] = None,
            norm1: Optional[float] = None, max_steps: Optional[int] = None,
-           three_term: bool = False) -> EvolveResult:
+           three_term: bool = False, sample_times=None) -> EvolveResult:
     """Alg. 1: approximate exp(-iHt) v0 with the a-posteriori bound of eq. errorIntegral.
 
     ``max_steps`` (harness use only, e.g. timing a bounded sample) stops after that many
     restarts and returns the state reached at t_reached < t.  ``three_term``: step 1 with the
-    printed recurrence only (see ``arnoldi``)."""
+    printed recurrence only (see ``arnoldi``).  ``sample_times`` (ascending, in [0, t]): the
+    states at those times from the basis and the small matrix of the step holding each of them
+    (second remark after Alg. 1): for t_now <= t_s <= t_now + t_step, v(t_s) = V exp(M (t_s -
+    t_now)) e_1; each comes with the bound accumulated up to the end of its step."""
     opts = opts or Options()
     if not (np.isfinite(t) and t >= 0.0) or not (np.isfinite(tol) and tol > 0.0) or m < 2:
         raise ValueError("need t >= 0 finite, tol > 0 finite, m >= 2")
@@ -248,8 +253,16 @@ def evolve(H, v0: np.ndarray, t: float, tol: float, m: int, opts: Optional[Optio
         raise ValueError("non-finite initial vector")
     d = v0.shape[0]
     beta0 = float(np.linalg.norm(v0))
+    ts = None if sample_times is None else np.asarray(sample_times, dtype=np.float64)
+    if ts is not None and (ts.ndim != 1 or np.any(ts < 0) or np.any(ts > t) or np.any(np.diff(ts) < 0)):
+        raise ValueError("sample times must be ascending and within [0, t]")
     if t == 0.0 or beta0 == 0.0:
-        return EvolveResult(v0.copy(), 0, 0, 0.0, 0.0, 0, 0, t)
+        smp = None if ts is None else np.repeat(v0[None, :], ts.size, axis=0)
+        return EvolveResult(v0.copy(), 0, 0, 0.0, 0.0, 0, 0, t, [], smp,
+                            None if ts is None else np.zeros(ts.size))
+    samples = None if ts is None else np.zeros((ts.size, d), dtype=np.complex128)
+    sample_bounds = None if ts is None else np.zeros(ts.size)
+    next_sample = 0
     if norm1 is None:
         norm1 = H.norm1() if hasattr(H, "norm1") else float(abs(H).sum(axis=0).max())
     w = v0 / beta0                                   # R8
@@ -278,6 +291,12 @@ def evolve(H, v0: np.ndarray, t: float, tol: float, m: int, opts: Optional[Optio
         if num_acc > err_acc:
             warnings |= WARN_NUMERICAL
         omega = krylov_coefficients(lam, U, tau)
+        t_end = t if (tau == t_rem or ar.breakdown) else t_now + tau
+        while ts is not None and next_sample < ts.size and ts[next_sample] <= t_end:
+            om_s = krylov_coefficients(lam, U, ts[next_sample] - t_now)
+            samples[next_sample] = beta0 * (ar.V @ om_s)
+            sample_bounds[next_sample] = beta0 * err_acc
+            next_sample += 1
         w = ar.V @ omega                             # step 3
         t_now = t if tau == t_rem else t_now + tau
         steps += 1
@@ -290,4 +309,4 @@ def evolve(H, v0: np.ndarray, t: float, tol: float, m: int, opts: Optional[Optio
         if max_steps is not None and steps >= max_steps:
             break
     return EvolveResult(beta0 * w, steps, matvecs, beta0 * err_acc, beta0 * num_acc, warnings,
-                        breakdown_dim, t_now, trace)
+                        breakdown_dim, t_now, trace, samples, sample_bounds)
