@@ -169,6 +169,33 @@ te_status te_set_allocator(te_alloc_fn alloc, te_free_fn free_fn, void* ctx);
 te_status te_evolve(te_hamiltonian h, const te_c128* v0, te_c128* v_out, double t, double tol,
                     int32_t m, const te_options* opt, te_result* res, void* stream);
 
+/* Intermediate-time sampling (second remark after Alg. 1): inside the step that holds t_s,
+ * v(t_s) = V exp(-i J (t_s - t_now)) e_1 from the step's own basis and small matrix, so the
+ * samples cost no extra Krylov builds.  Each sample carries the bound accumulated up to the
+ * end of its step (an upper bound at t_s).  Diagonal observables (e.g. number operators in a
+ * Fock basis) are reduced on the device without writing the states.
+ *   times    : host, n_times ascending values in [0, t].
+ *   states   : device, n_times x dim complex (state s at states + s*dim), or NULL.
+ *   obs      : device, n_obs x dim real diagonals D_o (D_o at obs + o*dim), or NULL if n_obs == 0.
+ *   obs_out  : host, n_times x n_obs: <v(t_s)| D_o |v(t_s)>.
+ *   bound_out: host, n_times, or NULL. */
+typedef struct {
+    int32_t n_times;
+    const double* times;
+    te_c128* states;
+    int32_t n_obs;
+    const double* obs;
+    double* obs_out;
+    double* bound_out;
+} te_samples;
+
+/* te_evolve plus samples (see te_samples).  Same arguments, results and errors as te_evolve;
+ * TE_ERR_INVALID_ARG for unsorted or out-of-range times and with TE_OPT_PROFILE.  Allocates
+ * O(n_times * (64 + n_obs * dim / 256)) scratch for the call.  Synchronous. */
+te_status te_evolve_sampled(te_hamiltonian h, const te_c128* v0, te_c128* v_out, double t, double tol,
+                            int32_t m, const te_options* opt, const te_samples* samples,
+                            te_result* res, void* stream);
+
 /* Totals recorded by the last te_evolve on h that ran with TE_OPT_PROFILE (zeros if none). */
 te_status te_last_profile(te_hamiltonian h, te_profile* out);
 

@@ -567,8 +567,41 @@ te_status te_hamiltonian_info(te_hamiltonian h, int64_t* dim, int64_t* nnz, doub
     return TE_OK;
 }
 
-te_status te_evolve(te_hamiltonian h, const te_c128* v0, te_c128* v_out, double t, double tol, int32_t m,
-                    const te_options* opt, te_result* res, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Device buffers of one sampled evolution (te_evolve_sampled).
+struct SampleBuffers {
+    int n = 0, n_obs = 0;
+    double* t = nullptr;        // [n] sample times
+    double2* omega = nullptr;   // [n][kMaxM]
+    double* bound = nullptr;    // [n]
+    double* obs_part = nullptr; // [n][n_obs][tiles]
+    double* obs_val = nullptr;  // [n][n_obs]
+    double2* states = nullptr;  // caller's [n][dim] or null
+    const double* obs = nullptr;
+    int tiles = 0;
+};
+
+hipError_t enqueue_restart_sampled(te_hamiltonian h, Workspace* w, const SampleBuffers& sb, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    for (int j = 0; j < w->m && e == hipSuccess; ++j) {
+        e = launch_project(w->tl, h->csr, w->V, w->ld, j, w->y, w->st, w->rb, s);
+        if (e == hipSuccess) e = launch_fold(j, w->st, w->rb, s);
+        if (e == hipSuccess) e = launch_update(w->tl, w->V, w->ld, w->dim, j, w->y, w->st, w->rb, s);
+    }
+    if (e == hipSuccess) e = launch_step(w->st, w->rb, w->host_flag_dev, s);
+    if (e == hipSuccess)  // the samples read the basis before the recombination overwrites column 0
+        e = launch_samples(w->tl.rpt_u, w->V, w->ld, w->dim, w->st, sb.states, sb.obs, sb.n_obs, sb.obs_part,
+                           sb.tiles, s);
+    if (e == hipSuccess) e = launch_combine(w->tl, w->V, w->ld, w->dim, w->st, s);
+    return e;
+}
+
+te_status evolve_impl(te_hamiltonian h, const te_c128* v0, te_c128* v_out, double t, double tol, int32_t m,
+                      const te_options* opt, te_result* res, void* stream, SampleBuffers* sb,
+                      DevState* header_out) {
     if (!h || !v0 || !v_out) return fail(TE_ERR_INVALID_ARG, "null pointer");
     if (!std::isfinite(t) || t < 0.0) return fail(TE_ERR_INVALID_ARG, "t must be finite and >= 0");
     if (!std::isfinite(tol) || !(tol > 0.0)) return fail(TE_ERR_INVALID_ARG, "tol must be finite and > 0");
@@ -586,8 +619,10 @@ te_status te_evolve(te_hamiltonian h, const te_c128* v0, te_c128* v_out, double 
     if (t == 0.0) {
         if (v_out != v0) TE_HIP(hipMemcpyAsync(v_out, v0, (size_t)dim * sizeof(te_c128), hipMemcpyDeviceToDevice, s));
         TE_HIP(hipStreamSynchronize(s));
+        if (header_out) header_out->beta0 = -1.0;  // not evolved
         return TE_OK;
     }
+    if (sb && (o.flags & TE_OPT_PROFILE)) return fail(TE_ERR_INVALID_ARG, "sampled evolution takes no TE_OPT_PROFILE");
     const int mm = std::min(m, dim);
     Workspace* w = nullptr;
     rc = get_workspace(h, mm, &w);
@@ -612,10 +647,20 @@ te_status te_evolve(te_hamiltonian h, const te_c128* v0, te_c128* v_out, double 
     }
     TE_HIP(launch_setup(w->st, prob, s));
     TE_HIP(launch_copy((const double2*)v0, w->V, dim, s));
+    if (sb) {
+        sb->tiles = w->tl.n_tiles_u;
+        const size_t part = (size_t)sb->n * (size_t)std::max(sb->n_obs, 1) * (size_t)sb->tiles * sizeof(double);
+        sb->obs_part = (double*)dev_alloc(part);
+        if (!sb->obs_part) return fail(TE_ERR_OUT_OF_MEMORY, "sample scratch allocation failed");
+        SampleState ss{sb->t, sb->omega, sb->bound, sb->n, 0, 0, 0};
+        TE_HIP(hipMemcpyAsync(&w->st->smp, &ss, sizeof(ss), hipMemcpyHostToDevice, s));
+        TE_HIP(hipStreamSynchronize(s));  // ss lives on this stack frame
+    }
     const long max_restarts = 100000000L;
     long r = 0;
     for (;; ++r) {
-        if (profile) TE_HIP(enqueue_restart_profiled(h, w, s, w->pev[r & 1]));
+        if (sb) TE_HIP(enqueue_restart_sampled(h, w, *sb, s));
+        else if (profile) TE_HIP(enqueue_restart_profiled(h, w, s, w->pev[r & 1]));
         else if (w->exec) TE_HIP(hipGraphLaunch(w->exec, s));
         else TE_HIP(enqueue_restart(h, w, s));
         TE_HIP(hipEventRecord(w->ev[r & 1], s));
@@ -633,7 +678,12 @@ te_status te_evolve(te_hamiltonian h, const te_c128* v0, te_c128* v_out, double 
     TE_HIP(launch_output(w->V, (double2*)v_out, dim, w->st, s));
     DevState hs;
     TE_HIP(hipMemcpyAsync(&hs, w->st, offsetof(DevState, alpha), hipMemcpyDeviceToHost, s));
+    if (sb) {
+        TE_HIP(hipMemcpyAsync(&hs.smp, &w->st->smp, sizeof(SampleState), hipMemcpyDeviceToHost, s));
+        if (sb->n_obs > 0) TE_HIP(launch_obs_fold(sb->obs_part, sb->tiles, sb->n * sb->n_obs, sb->obs_val, s));
+    }
     TE_HIP(hipStreamSynchronize(s));
+    if (header_out) *header_out = hs;
     if (res) {
         res->steps = hs.steps;
         res->matvecs = hs.matvecs;
@@ -670,6 +720,99 @@ te_status te_evolve(te_hamiltonian h, const te_c128* v0, te_c128* v_out, double 
     if (hs.beta0 != 0.0 && hs.t_now != t)
         return fail(TE_ERR_DEVICE, "evolution stopped at t=" + std::to_string(hs.t_now) + " before reaching t");
     return TE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+te_status te_evolve(te_hamiltonian h, const te_c128* v0, te_c128* v_out, double t, double tol, int32_t m,
+                    const te_options* opt, te_result* res, void* stream) {
+    return evolve_impl(h, v0, v_out, t, tol, m, opt, res, stream, nullptr, nullptr);
+}
+
+te_status te_evolve_sampled(te_hamiltonian h, const te_c128* v0, te_c128* v_out, double t, double tol,
+                            int32_t m, const te_options* opt, const te_samples* smp, te_result* res,
+                            void* stream) {
+    if (!h || !v0 || !v_out || !smp) return fail(TE_ERR_INVALID_ARG, "null pointer");
+    const int n = smp->n_times, n_obs = smp->n_obs;
+    if (n < 0 || n_obs < 0) return fail(TE_ERR_INVALID_ARG, "negative sample or observable count");
+    if (n == 0) return te_evolve(h, v0, v_out, t, tol, m, opt, res, stream);
+    if (!smp->times) return fail(TE_ERR_INVALID_ARG, "null sample times");
+    if (n_obs > 0 && (!smp->obs || !smp->obs_out)) return fail(TE_ERR_INVALID_ARG, "null observable pointer");
+    if (!std::isfinite(t) || t < 0.0) return fail(TE_ERR_INVALID_ARG, "t must be finite and >= 0");
+    for (int i = 0; i < n; ++i) {
+        const double ti = smp->times[i];
+        if (!(ti >= 0.0 && ti <= t) || (i > 0 && ti < smp->times[i - 1]))
+            return fail(TE_ERR_INVALID_ARG, "sample times must be ascending and within [0, t]");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const int dim = h->csr.dim;
+    SampleBuffers sb;
+    sb.n = n;
+    sb.n_obs = n_obs;
+    sb.states = (double2*)smp->states;
+    sb.obs = smp->obs;
+    sb.t = (double*)dev_alloc((size_t)n * sizeof(double));
+    sb.omega = (double2*)dev_alloc((size_t)n * kMaxM * sizeof(double2));
+    sb.bound = (double*)dev_alloc((size_t)n * sizeof(double));
+    sb.obs_val = (double*)dev_alloc((size_t)n * std::max(n_obs, 1) * sizeof(double));
+    auto release = [&]() {
+        (void)hipStreamSynchronize(s);
+        dev_free(sb.t);
+        dev_free(sb.omega);
+        dev_free(sb.bound);
+        dev_free(sb.obs_part);
+        dev_free(sb.obs_val);
+    };
+    if (!sb.t || !sb.omega || !sb.bound || !sb.obs_val) {
+        release();
+        return fail(TE_ERR_OUT_OF_MEMORY, "sample buffer allocation failed");
+    }
+    te_status rc = TE_OK;
+    auto chk = [&](hipError_t e, const char* what) {
+        if (e != hipSuccess && rc == TE_OK) rc = fail(TE_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    };
+    chk(hipMemcpyAsync(sb.t, smp->times, (size_t)n * sizeof(double), hipMemcpyHostToDevice, s), "copy times");
+    chk(hipStreamSynchronize(s), "hipStreamSynchronize");
+    DevState hs;
+    std::memset(&hs, 0, offsetof(DevState, alpha));
+    if (rc == TE_OK) rc = evolve_impl(h, v0, v_out, t, tol, m, opt, res, stream, &sb, &hs);
+    if (rc == TE_OK && (hs.beta0 == -1.0 || hs.beta0 == 0.0)) {
+        // t = 0: every sample is v0; ||v0|| = 0: every sample is zero
+        const bool zero = hs.beta0 == 0.0;
+        for (int i = 0; i < n && smp->states; ++i) {
+            double2* dst = (double2*)smp->states + (size_t)i * dim;
+            if (zero) chk(hipMemsetAsync(dst, 0, (size_t)dim * sizeof(double2), s), "clear state");
+            else chk(hipMemcpyAsync(dst, v0, (size_t)dim * sizeof(double2), hipMemcpyDeviceToDevice, s), "copy v0");
+        }
+        std::vector<double> vals((size_t)std::max(n_obs, 1), 0.0);
+        if (!zero && n_obs > 0 && rc == TE_OK) {
+            const int tiles = (dim + kBlock - 1) / kBlock;
+            sb.obs_part = (double*)dev_alloc((size_t)n_obs * tiles * sizeof(double));
+            if (!sb.obs_part) rc = fail(TE_ERR_OUT_OF_MEMORY, "sample scratch allocation failed");
+            if (rc == TE_OK) chk(launch_expect((const double2*)v0, dim, sb.obs, n_obs, sb.obs_part, tiles, s), "expect");
+            if (rc == TE_OK) chk(launch_obs_fold(sb.obs_part, tiles, n_obs, sb.obs_val, s), "fold");
+            if (rc == TE_OK)
+                chk(hipMemcpyAsync(vals.data(), sb.obs_val, (size_t)n_obs * sizeof(double), hipMemcpyDeviceToHost, s),
+                    "copy observables");
+            chk(hipStreamSynchronize(s), "hipStreamSynchronize");
+        }
+        for (int i = 0; i < n && rc == TE_OK; ++i) {
+            for (int o = 0; o < n_obs; ++o) smp->obs_out[(size_t)i * n_obs + o] = vals[(size_t)o];
+            if (smp->bound_out) smp->bound_out[i] = 0.0;
+        }
+    } else if (rc == TE_OK) {
+        if (hs.smp.next != n) rc = fail(TE_ERR_DEVICE, "not every sample time was reached");
+        if (rc == TE_OK && n_obs > 0)
+            chk(hipMemcpyAsync(smp->obs_out, sb.obs_val, (size_t)n * n_obs * sizeof(double), hipMemcpyDeviceToHost, s),
+                "copy observables");
+        if (rc == TE_OK && smp->bound_out)
+            chk(hipMemcpyAsync(smp->bound_out, sb.bound, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, s),
+                "copy bounds");
+    }
+    release();
+    return rc;
 }
 
 te_status te_autotune(te_hamiltonian h, int32_t m, te_tuning* out, void* stream) {

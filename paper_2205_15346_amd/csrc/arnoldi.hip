@@ -74,6 +74,13 @@ __device__ __forceinline__ void setup_state(DevState* __restrict__ st, const Pro
     st->h = 0.0;
     st->ys = 1.0;
     st->s[0] = 1.0;
+    st->smp.t = nullptr;
+    st->smp.omega = nullptr;
+    st->smp.bound = nullptr;
+    st->smp.n = 0;
+    st->smp.next = 0;
+    st->smp.lo = 0;
+    st->smp.hi = 0;
 }
 
 __global__ void k_setup(DevState* __restrict__ st, Problem prob) {
@@ -82,17 +89,6 @@ __global__ void k_setup(DevState* __restrict__ st, Problem prob) {
 
 __global__ __launch_bounds__(kBlock) void k_copy(const double2* __restrict__ src, double2* __restrict__ dst, int dim) {
     for (int r = blockIdx.x * kBlock + threadIdx.x; r < dim; r += gridDim.x * kBlock) dst[r] = src[r];
-}
-
-// Basis columns are streamed once per pass and not reused before the pass ends, so they are
-// read with non-temporal loads: they then do not evict the CSR arrays and the product vector
-// from the caches, which the next sparse product reads again (measured: a sparse product after a
-// 40-column pass runs 14% faster when that pass used non-temporal loads).
-__device__ __forceinline__ double2 load_stream(const double2* p) {
-    double2 v;
-    v.x = __builtin_nontemporal_load(&p->x);
-    v.y = __builtin_nontemporal_load(&p->y);
-    return v;
 }
 
 // -------------------------------------------------------------- project: SpMV + projections

@@ -378,9 +378,47 @@ __device__ void write_omega(DevState* st, int k, double tau, bool scale_raw, Ste
     }
 }
 
+// Krylov coefficients of the sample times this step covers (t_s <= t_end), computed like
+// omega with tau = t_s - t_now, and the bound at the end of the step for each of them.
+__device__ void sample_coefficients(DevState* st, int k, double t_now, double t_end, double bound,
+                                    StepShared& sh) {
+    __shared__ int lo_sh, hi_sh;
+    if (threadIdx.x == 0) {
+        const int n = st->smp.n;
+        int s = st->smp.next;
+        while (s < n && st->smp.t[s] <= t_end) ++s;
+        lo_sh = st->smp.next;
+        hi_sh = s;
+        st->smp.lo = lo_sh;
+        st->smp.hi = s;
+        st->smp.next = s;
+    }
+    __syncthreads();
+    const int lo = lo_sh, cnt = hi_sh - lo_sh;
+    for (int p = threadIdx.x; p < cnt * k; p += blockDim.x) {
+        const int smp = lo + p / k, i = p % k;
+        const double dt = st->smp.t[smp] - t_now;
+        double re = 0.0, im = 0.0;
+        for (int n = 0; n < k; ++n) {
+            double sn, cn;
+            sincos(sh.lam[n] * dt, &sn, &cn);
+            const double a = sh.Qt[n * 64 + i] * sh.Qt[n * 64];
+            re = fma(a, cn, re);
+            im = fma(-a, sn, im);
+        }
+        const double sc = st->s[i];
+        st->smp.omega[(size_t)smp * kMaxM + i] = make_double2(re * sc, im * sc);
+        if (i == 0) st->smp.bound[smp] = bound;
+    }
+}
+
 __device__ void step_body(DevState* st, int* host_flag, bool controller) {
     __shared__ StepShared sh;
     const int tid = threadIdx.x;
+    if (tid == 0) {  // no samples unless this step assigns some
+        st->smp.lo = 0;
+        st->smp.hi = 0;
+    }
     if (st->done) {
         if (tid == 0) {
             st->do_combine = 0;
@@ -420,6 +458,10 @@ __device__ void step_body(DevState* st, int* host_flag, bool controller) {
         return;
     }
     write_omega(st, k, so.tau, controller, sh);
+    if (controller && st->smp.n > 0) {
+        const double t_end = (so.tau == t_rem || breakdown) ? P.t : t_now + so.tau;
+        sample_coefficients(st, k, t_now, t_end, st->beta0 * (st->err_acc + so.err), sh);
+    }
     __syncthreads();
     if (tid == 0) {
         st->last_tau = so.tau;

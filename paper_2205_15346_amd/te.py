@@ -110,6 +110,12 @@ class te_engine_stats(ctypes.Structure):
         return d
 
 
+class te_samples(ctypes.Structure):
+    _fields_ = [("n_times", ctypes.c_int32), ("times", ctypes.c_void_p), ("states", ctypes.c_void_p),
+                ("n_obs", ctypes.c_int32), ("obs", ctypes.c_void_p), ("obs_out", ctypes.c_void_p),
+                ("bound_out", ctypes.c_void_p)]
+
+
 class TEError(RuntimeError):
     def __init__(self, status, message):
         super().__init__(f"{message} (status {status})")
@@ -139,6 +145,8 @@ _SIGS = {
     "te_set_allocator": (_I, [_P, _P, _P]),
     "te_evolve": (_I, [_P, _P, _P, _D, _D, _I, ctypes.POINTER(te_options), ctypes.POINTER(te_result), _P]),
     "te_last_profile": (_I, [_P, ctypes.POINTER(te_profile)]),
+    "te_evolve_sampled": (_I, [_P, _P, _P, _D, _D, _I, ctypes.POINTER(te_options), ctypes.POINTER(te_samples),
+                               ctypes.POINTER(te_result), _P]),
     "te_autotune": (_I, [_P, _I, ctypes.POINTER(te_tuning), _P]),
     "te_get_tuning": (_I, [_P, ctypes.POINTER(te_tuning)]),
     "te_set_tuning": (_I, [_P, ctypes.POINTER(te_tuning)]),
@@ -282,6 +290,38 @@ def te_evolve(H: Hamiltonian, v0, t: float, tol: float, m: int, options=None, ou
     opt = ctypes.byref(options) if options is not None else None
     _check(_lib.te_evolve(H.handle, p0, p1, float(t), float(tol), int(m), opt, ctypes.byref(res), _stream(stream)))
     return out, res
+
+
+def te_evolve_sampled(H: Hamiltonian, v0, t: float, tol: float, m: int, times, states=True, obs=None,
+                      options=None, out=None, stream=None):
+    """v(t) plus the states and/or diagonal observables at the given times: returns
+    (v_out tensor, te_result, states tensor [n, dim] or None, observables [n, n_obs] or None,
+    bounds [n])."""
+    import torch
+    p0 = _dev_c128(v0, "v0", H.dim)
+    if out is None:
+        out = torch.empty_like(v0)
+    p1 = _dev_c128(out, "out", H.dim)
+    ts = np.ascontiguousarray(times, dtype=np.float64)
+    n = ts.size
+    st = torch.empty((n, H.dim), dtype=torch.complex128, device=v0.device) if states else None
+    n_obs = 0
+    obs_out = None
+    if obs is not None:
+        if not (isinstance(obs, torch.Tensor) and obs.is_cuda and obs.dtype == torch.float64 and obs.is_contiguous()
+                and obs.dim() == 2 and obs.shape[1] == H.dim):
+            raise TypeError("obs must be a contiguous float64 CUDA tensor [n_obs, dim]")
+        n_obs = obs.shape[0]
+        obs_out = np.zeros((n, n_obs))
+    bounds = np.zeros(n)
+    smp = te_samples(n, ts.ctypes.data, st.data_ptr() if st is not None else None, n_obs,
+                     obs.data_ptr() if obs is not None else None,
+                     obs_out.ctypes.data if obs_out is not None else None, bounds.ctypes.data)
+    res = te_result()
+    opt = ctypes.byref(options) if options is not None else None
+    _check(_lib.te_evolve_sampled(H.handle, p0, p1, float(t), float(tol), int(m), opt, ctypes.byref(smp),
+                                  ctypes.byref(res), _stream(stream)))
+    return out, res, st, obs_out, bounds
 
 
 def te_autotune(H: Hamiltonian, m: int, stream=None) -> te_tuning:
