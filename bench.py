@@ -177,80 +177,157 @@ def bench_batch(te, torch, dev, n_instances, m, profile):
     return rec
 
 
-def bench_serving(te, torch, dev, n_requests, qps, m, budget_gb):
+def serve_engine(te, torch, hs, reqs, v0, m, budget_gb, arrivals, label):
+    """Submit reqs at the given arrival times (seconds from the start) into a threaded engine;
+    returns per-request (submitted, finished, info, result) and the engine stats."""
+    small = min(hs.values(), key=lambda h: h.dim)
+    vw = torch.zeros(small.dim, dtype=torch.complex128, device=v0[0].device)
+    vw[0] = 1.0
+    with te.Engine(int(budget_gb * 1e9), m=m, max_jobs=256) as eng:
+        w = eng.submit(small, vw, 1.0, 1e-8)  # warm-up (kernels, tuning)
+        eng.wait(w, timeout=600)
+        torch.cuda.synchronize()
+        ids = []
+        t0 = time.perf_counter()
+        for i, (r, v, at) in enumerate(zip(reqs, v0, arrivals)):
+            delay = at - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+            ids.append(eng.submit(hs[r.hamiltonian_key()], v, r.t, r.tol))
+            if (i + 1) % 25 == 0:
+                log(f"[bench] {label}: {i + 1} requests submitted")
+        while True:
+            try:
+                eng.wait(-1, timeout=30.0)
+                break
+            except te.TEError as e:
+                if e.status != te.TE_ERR_TIMEOUT:
+                    raise
+                st = eng.stats()
+                log(f"[bench] {label}: {st.jobs_done} done, {st.jobs_running} running, {st.jobs_queued} queued")
+        infos = [eng.poll(j) for j in ids]
+        outs = [eng.output(j).clone() for j in ids]
+        st = eng.stats()
+    return infos, outs, st
+
+
+def latency_summary(lat):
+    return {"p50": 1e3 * percentile(lat, 50), "p99": 1e3 * percentile(lat, 99)}
+
+
+def bench_serving(te, torch, dev, n_requests, qps, m, budget_gb, sweep=(), sweep_requests=48,
+                  saturation=False):
     """Poisson arrivals of XXZ (L 14..22) and Bose (K=N 10..12) requests into the threaded engine
     (continuous batching, admission by footprint), against the same stream served one request at a
-    time by te_evolve (FIFO; completion = max(arrival, previous completion) + measured solve time)."""
+    time by te_evolve (FIFO: completion = max(arrival, previous completion) + measured solve time).
+    The draws of kind, size, t and tol do not depend on the QPS (only the gaps scale), so one set
+    of one-at-a-time solve times serves every QPS.  saturation: all requests at time 0 first, and
+    qps <= 0 then means 70% of the saturation throughput."""
     import workloads
-    reqs = workloads.serving_requests(n_requests, qps)
+    n_max = max([n_requests] + ([sweep_requests] if sweep else []))
+    base = workloads.serving_requests(n_max, 1.0)  # arrivals at 1 QPS; scaled below
     hs = {}
     b0 = time.perf_counter()
-    for r in reqs:
+    for r in base:
         key = r.hamiltonian_key()
         if key not in hs:
             H = workloads.configs.serving_hamiltonian(*key)
             hs[key] = te.te_hamiltonian_create(H.row_ptr, H.col, H.val)
             del H
-    v0 = [torch.from_numpy(r.v0(hs[r.hamiltonian_key()].dim)).to(dev) for r in reqs]
-    log(f"[bench] serving: {len(reqs)} requests at {qps} qps over {len(hs)} Hamiltonians "
-        f"(built in {time.perf_counter() - b0:.1f} s)")
-    # warm-up: one small request through each path
+    v0 = [torch.from_numpy(r.v0(hs[r.hamiltonian_key()].dim)).to(dev) for r in base]
+    log(f"[bench] serving: up to {n_max} requests over {len(hs)} Hamiltonians (built in {time.perf_counter() - b0:.1f} s)")
+
+    # one request at a time through te_evolve: service times (also the reference results)
     small = min(hs.values(), key=lambda h: h.dim)
     vw = torch.zeros(small.dim, dtype=torch.complex128, device=dev)
     vw[0] = 1.0
     te.te_evolve(small, vw, 1.0, 1e-8, m)
-    with te.Engine(int(budget_gb * 1e9), m=m, max_jobs=256) as eng:
-        w = eng.submit(small, vw, 1.0, 1e-8)
-        eng.wait(w, timeout=600)
+    service, ref = [], []
+    for i, (r, v) in enumerate(zip(base, v0)):
         torch.cuda.synchronize()
-        ids = []
-        t0 = time.perf_counter()
-        for r, v in zip(reqs, v0):
-            delay = r.arrival - (time.perf_counter() - t0)
-            if delay > 0:
-                time.sleep(delay)
-            ids.append(eng.submit(hs[r.hamiltonian_key()], v, r.t, r.tol))
-        eng.wait(-1, timeout=3000)
-        infos = [eng.poll(j) for j in ids]
-        outs = [eng.output(j) for j in ids]
-        st = eng.stats()
+        s0 = time.perf_counter()
+        out, rr = te.te_evolve(hs[r.hamiltonian_key()], v, r.t, r.tol, m)
+        torch.cuda.synchronize()
+        service.append(time.perf_counter() - s0)
+        ref.append((out.clone(), rr.err_bound))
+        if (i + 1) % 25 == 0:
+            log(f"[bench] one at a time: {i + 1} requests")
+
+    def fifo(arrivals, n):
+        done, lat = 0.0, []
+        for at, sv in zip(arrivals[:n], service[:n]):
+            done = max(done, at) + sv
+            lat.append(done - at)
+        return n / (done - arrivals[0]), lat
+
+    def run(n, q, label):
+        reqs = base[:n]
+        arrivals = [0.0] * n if q is None else [r.arrival / q for r in reqs]
+        infos, outs, st = serve_engine(te, torch, hs, reqs, v0[:n], m, budget_gb, arrivals, label)
         first = min(i.submitted for i, _ in infos)
         last = max(i.finished for i, _ in infos)
         lat = [i.finished - i.submitted for i, _ in infos]
-        served_s = last - first
-        failed = sum(1 for i, _ in infos if i.state != te.TE_JOB_DONE)
-        log(f"[bench] serving: {served_s:.2f} s, {len(reqs) / served_s:.2f} states/s, p50 {percentile(lat, 50):.3f} s "
-            f"p99 {percentile(lat, 99):.3f} s, rounds={st.rounds} plans={st.plans} pool peak {st.pool_peak / 1e9:.1f} GB")
-        # the same requests one at a time
-        service, worst = [], 0.0
-        for r, v, o, (_, res) in zip(reqs, v0, outs, infos):
-            torch.cuda.synchronize()
-            s = time.perf_counter()
-            out, rr = te.te_evolve(hs[r.hamiltonian_key()], v, r.t, r.tol, m)
-            torch.cuda.synchronize()
-            service.append(time.perf_counter() - s)
-            worst = max(worst, float((out - o).norm()) / max(rr.err_bound + res.err_bound, 1e-300))
-    done, fifo_lat = 0.0, []
-    for r, sv in zip(reqs, service):
-        done = max(done, r.arrival) + sv
-        fifo_lat.append(done - r.arrival)
-    fifo_span = done - reqs[0].arrival
-    log(f"[bench] one at a time (FIFO): {len(reqs) / fifo_span:.2f} states/s, p50 {percentile(fifo_lat, 50):.3f} s "
-        f"p99 {percentile(fifo_lat, 99):.3f} s")
+        worst = max(float((o - ref[k][0]).norm()) / max(ref[k][1] + infos[k][1].err_bound, 1e-300)
+                    for k, o in enumerate(outs))
+        f_rate, f_lat = fifo(arrivals, n)
+        rec = {"requests": n, "qps": q, "states_per_s": n / (last - first), "seconds": last - first,
+               "latency_ms": latency_summary(lat),
+               "one_at_a_time_fifo": {"states_per_s": f_rate, "latency_ms": latency_summary(f_lat)},
+               "rounds": st.rounds, "plans": st.plans, "pool_peak_gb": st.pool_peak / 1e9,
+               "failed": sum(1 for i, _ in infos if i.state != te.TE_JOB_DONE),
+               "max_diff_over_bounds_vs_one_at_a_time": worst}
+        log(f"[bench] {label}: {rec['states_per_s']:.2f} states/s, p50 {rec['latency_ms']['p50'] / 1e3:.3f} s, "
+            f"p99 {rec['latency_ms']['p99'] / 1e3:.3f} s | one at a time {f_rate:.2f} states/s, "
+            f"p50 {rec['one_at_a_time_fifo']['latency_ms']['p50'] / 1e3:.3f} s, "
+            f"p99 {rec['one_at_a_time_fifo']['latency_ms']['p99'] / 1e3:.3f} s")
+        return rec
+
+    out = {"m": m, "hbm_budget_gb": budget_gb,
+           "mean_service_ms": 1e3 * sum(service[:n_requests]) / n_requests,
+           "one_at_a_time_saturation_states_per_s": n_requests / sum(service[:n_requests])}
+    if saturation:
+        sat = run(n_requests, None, "saturation (all requests at t=0)")
+        out["saturation"] = sat
+        if qps <= 0:
+            qps = 0.7 * sat["states_per_s"]
+    main = run(n_requests, qps, f"serving {n_requests} at {qps:.2f} qps")
+    out.update({"workload": f"serving_{n_requests}_at_{qps:.2f}qps", **main})
+    if sweep:
+        out["sweep"] = [run(sweep_requests, q, f"sweep {sweep_requests} at {q} qps") for q in sweep]
     for h in hs.values():
         h.destroy()
-    return {
-        "workload": f"serving_{n_requests}_at_{qps}qps",
-        "requests": len(reqs), "qps": qps, "m": m, "hbm_budget_gb": budget_gb,
-        "states_per_s": len(reqs) / served_s, "seconds": served_s,
-        "latency_ms": {"p50": 1e3 * percentile(lat, 50), "p99": 1e3 * percentile(lat, 99)},
-        "one_at_a_time_fifo": {"states_per_s": len(reqs) / fifo_span,
-                               "latency_ms": {"p50": 1e3 * percentile(fifo_lat, 50),
-                                              "p99": 1e3 * percentile(fifo_lat, 99)},
-                               "mean_service_ms": 1e3 * sum(service) / len(service)},
-        "rounds": st.rounds, "plans": st.plans, "failed": failed, "pool_peak_gb": st.pool_peak / 1e9,
-        "max_diff_over_bounds_vs_one_at_a_time": worst,
-    }
+    return out
+
+
+def bench_paper_model(te, torch, dev):
+    """The paper's own performance example (Sec. "Analysis of Performance"): eq. fullHamiltonianSimple
+    with K = K' = 10, N_m = 5, N_0 = N_c = 100 (d = 1,565,904), the initial state of eq.
+    initialStateSimple, t = 10, m = 40, err_max = 1e-7.  The paper's figure (one CPU thread of an
+    i9-9900K, 353 s; roundoff estimate 3.2e-6) is context, not a comparison on equal hardware."""
+    import workloads
+    b0 = time.perf_counter()
+    H, v0, _ = workloads.memory_burden_model(K=10, Kp=10, Nm=5, N0=100, Nc=100.0)
+    build_s = time.perf_counter() - b0
+    h = te.te_hamiltonian_create(H.row_ptr, H.col, H.val)
+    x = torch.from_numpy(v0).to(dev)
+    dim, nnz = H.dim, H.nnz
+    del H
+    te.te_evolve(h, x, 10.0, 1e-7, 40)  # warm-up and autotune
+    times = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        _, res = te.te_evolve(h, x, 10.0, 1e-7, 40)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - s0)
+    h.destroy()
+    sec = sum(times) / len(times)
+    log(f"[bench] paper model d={dim}: {sec:.3f} s per solve, restarts={res.steps}, bound={res.err_bound:.2e}, "
+        f"roundoff estimate={res.num_err_estimate:.2e}")
+    return {"dim": dim, "nnz": nnz, "t": 10.0, "tol": 1e-7, "m": 40, "seconds_per_solve": sec,
+            "restarts": res.steps, "err_bound": res.err_bound, "num_err_estimate": res.num_err_estimate,
+            "warnings": res.warnings, "build_seconds_host": build_s,
+            "paper_context": {"seconds_one_cpu_thread_i9_9900K": 353.0, "num_err_estimate": 3.2e-6}}
 
 
 def main():
@@ -267,8 +344,13 @@ def main():
     ap.add_argument("--batch-instances", type=int, default=256, help="instances of the XXZ batch (0: skip)")
     ap.add_argument("--batch-profile", type=int, default=1, help="also run the batch in profiling mode")
     ap.add_argument("--serve-requests", type=int, default=16, help="requests of the serving run (0: skip)")
-    ap.add_argument("--serve-qps", type=float, default=2.0)
+    ap.add_argument("--serve-qps", type=float, default=2.0, help="arrival rate; <= 0: 70%% of the saturation rate")
     ap.add_argument("--serve-budget-gb", type=float, default=96.0)
+    ap.add_argument("--serve-saturation", type=int, default=0, help="first measure saturation (all arrive at 0)")
+    ap.add_argument("--serve-sweep", default="", help="comma-separated QPS values for a sweep")
+    ap.add_argument("--serve-sweep-requests", type=int, default=48)
+    ap.add_argument("--paper-model", type=int, default=0,
+                    help="also time the paper's own performance example (d = 1,565,904; ~1 min to build)")
     args = ap.parse_args()
     if args.gpus != 1:
         log("bench.py measures one GPU: this build has no multi-GPU path (independent solves shard "
@@ -346,7 +428,10 @@ def main():
     if args.batch_instances > 0:
         batch = bench_batch(te, torch, dev, args.batch_instances, wl.m, bool(args.batch_profile))
     if args.serve_requests > 0:
-        serving = bench_serving(te, torch, dev, args.serve_requests, args.serve_qps, wl.m, args.serve_budget_gb)
+        sweep = [float(x) for x in args.serve_sweep.split(",") if x.strip()]
+        serving = bench_serving(te, torch, dev, args.serve_requests, args.serve_qps, wl.m, args.serve_budget_gb,
+                                sweep, args.serve_sweep_requests, bool(args.serve_saturation) or args.serve_qps <= 0)
+    paper = bench_paper_model(te, torch, dev) if args.paper_model else None
 
     cpu = None
     if args.cpu_restarts > 0:
@@ -401,6 +486,7 @@ def main():
         "three_term_mode": three_term,
         "batch": batch,
         "serving": serving,
+        "paper_model": paper,
     }
     print(json.dumps(line), flush=True)
 
