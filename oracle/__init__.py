@@ -8,7 +8,8 @@ and it shares no code, tables or constants with the HIP library.
 
 Modules
   quadrature  adaptive tanh-sinh rule for the error integral (Sec. "Improvement of
-              Error Bound", eq. errorIntegral; Alg. 1 step 2)
+              Error Bound", eq. errorIntegral; Alg. 1 step 2) and the fast non-adaptive
+              Gauss-Legendre option (Sec. "Description of Program")
   krylov      Alg. 1: Arnoldi step on A = -iH (eq. arnoldi), diagonalisation of the
               Hessenberg matrix, step-size search (eqs. errorRate, stepSize) and the
               restart loop, plus the roundoff estimate of eq. numericalError.
@@ -20,13 +21,13 @@ solutions, closed forms, invariants, an arbitrary-precision quadrature, the
 paper's forward-backward example); none is "parity unpinned".
 """
 
-from .quadrature import tanh_sinh, QuadratureResult
+from .quadrature import gauss_legendre, tanh_sinh, QuadratureResult
 from .krylov import (Options, ArnoldiResult, EvolveResult, StepUnderflow, WARN_NUMERICAL,
                      WARN_QUADRATURE, spmv, arnoldi, hessenberg_eig, bound_integrand,
                      step_size, krylov_coefficients, evolve, hessenberg_from_lanczos)
 
 __all__ = [
-    "tanh_sinh", "QuadratureResult", "Options", "ArnoldiResult", "EvolveResult", "StepUnderflow",
+    "tanh_sinh", "gauss_legendre", "QuadratureResult", "Options", "ArnoldiResult", "EvolveResult", "StepUnderflow",
     "WARN_NUMERICAL", "WARN_QUADRATURE", "spmv", "arnoldi", "hessenberg_eig", "bound_integrand",
     "step_size", "krylov_coefficients", "evolve", "hessenberg_from_lanczos",
 ]

@@ -36,6 +36,10 @@ Readings adopted where the paper is silent, ambiguous or garbled:
       f = h |sum_n c_n exp(-i lam_n tau)| with sum_n |c_n| <= 1.
   R9  tol = err_max bounds the 2-norm of the final error; the reported bound is
       the sum of the per-step integrals (unitarity makes local errors add).
+  R14 The fast integration option (Sec. "Description of Program": a non-adaptive Gauss
+      scheme) is the n-point Gauss-Legendre rule on each integration interval, n chosen by
+      the user (the paper gives no count); it has no error estimate, so the bound it yields
+      is an approximation of the rigorous one.
 """
 
 from dataclasses import dataclass, field
@@ -43,7 +47,7 @@ from typing import List, Optional
 
 import numpy as np
 
-from .quadrature import tanh_sinh
+from .quadrature import gauss_legendre, tanh_sinh
 
 WARN_NUMERICAL = 1
 WARN_QUADRATURE = 2
@@ -63,6 +67,7 @@ class Options:
     quad_max_level: int = 15
     quad_min_level: int = 3
     max_halvings: int = 64
+    quad_gauss_points: int = 0   # > 0: the paper's fast non-adaptive Gauss option (R14)
 
 
 @dataclass
@@ -182,6 +187,8 @@ def step_size(f, tol_rate: float, t_rem: float, first: bool, tau_prev: float, br
     ok = [True]
 
     def integral(a, b):
+        if opts.quad_gauss_points > 0:
+            return gauss_legendre(f, a, b, opts.quad_gauss_points).value
         res = tanh_sinh(f, a, b, opts.quad_rel_tol, opts.quad_max_level, opts.quad_min_level,
                         noise_rate * (b - a))
         ok[0] &= res.converged
