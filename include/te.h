@@ -67,7 +67,7 @@ enum {
 
 /* Tunable constants of the step-size search (Alg. 1 step 2).  te_default_options()
  * fills: n_substeps=10, t_init=0.1, shrink=0.97, quad_rel_tol=1e-3, quad_max_level=15,
- * quad_min_level=3, max_halvings=64. */
+ * quad_min_level=3, max_halvings=64, flags=0, quad_gauss_points=0. */
 typedef struct {
     int32_t n_substeps;     /* N_SUBSTEPS of Alg. 1 */
     double t_init;          /* first step-size guess (Alg. 1 line 1) */
@@ -77,6 +77,10 @@ typedef struct {
     int32_t quad_min_level; /* refinements always taken */
     int32_t max_halvings;   /* cap of the halving loop (TE_ERR_STEP_UNDERFLOW) */
     uint32_t flags;         /* TE_OPT_* bits (below); other bits must be 0 */
+    int32_t quad_gauss_points; /* 0: adaptive tanh-sinh (rigorous to its tolerance); 1..64: the
+                                  paper's fast option (Sec. "Description of Program"), an
+                                  n-point Gauss-Legendre rule per integral with no error
+                                  estimate, so the reported bound is approximate */
 } te_options;
 
 typedef struct {

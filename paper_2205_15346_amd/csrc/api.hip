@@ -432,13 +432,15 @@ Problem make_problem(const te_hamiltonian_s* h, const te_options& o, double t, d
     p.quad_min_level = o.quad_min_level;
     p.max_halvings = o.max_halvings;
     p.three_term = (o.flags & TE_OPT_LANCZOS3) ? 1 : 0;
+    p.gauss_n = o.quad_gauss_points;
     return p;
 }
 
 te_status check_options(const te_options& o) {
     if (o.n_substeps < 1 || !(o.t_init > 0.0) || !std::isfinite(o.t_init) || !(o.shrink > 0.0) || !(o.shrink <= 1.0) ||
         !(o.quad_rel_tol > 0.0) || o.quad_max_level < 0 || o.quad_max_level > 20 || o.quad_min_level < 0 ||
-        o.max_halvings < 0 || (o.flags & ~(TE_OPT_PROFILE | TE_OPT_LANCZOS3)) != 0)
+        o.max_halvings < 0 || (o.flags & ~(TE_OPT_PROFILE | TE_OPT_LANCZOS3)) != 0 || o.quad_gauss_points < 0 ||
+        o.quad_gauss_points > TE_MAX_KRYLOV)
         return fail(TE_ERR_INVALID_ARG, "invalid te_options");
     return TE_OK;
 }
@@ -458,6 +460,7 @@ void te_default_options(te_options* o) {
     o->quad_min_level = 3;
     o->max_halvings = 64;
     o->flags = 0;
+    o->quad_gauss_points = 0;
 }
 
 const char* te_status_string(te_status s) {
@@ -968,6 +971,7 @@ te_status te_error_integral(int32_t k, const double* lambda, const double* coef,
     p.quad_rel_tol = o.quad_rel_tol;
     p.quad_max_level = o.quad_max_level;
     p.quad_min_level = o.quad_min_level;
+    p.gauss_n = o.quad_gauss_points;
     const size_t n = (size_t)k;
     double* d = (double*)dev_alloc((2 * n + 4) * sizeof(double));
     if (!d) return fail(TE_ERR_OUT_OF_MEMORY, "device allocation failed");
@@ -1016,6 +1020,7 @@ te_status te_step_search(int32_t k, const double* alpha, const double* beta, dou
     p.quad_max_level = o.quad_max_level;
     p.quad_min_level = o.quad_min_level;
     p.max_halvings = o.max_halvings;
+    p.gauss_n = o.quad_gauss_points;
     hs->k_limit = k;
     hs->h = h;
     hs->breakdown = breakdown ? 1 : 0;

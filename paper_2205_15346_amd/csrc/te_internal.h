@@ -29,7 +29,7 @@ struct Problem {
     int32_t m, dim;
     int32_t n_substeps, quad_max_level, quad_min_level, max_halvings;
     int32_t three_term;  // Krylov step: 0 full re-orthogonalisation, 1 three-term recurrence only
-    int32_t pad_;
+    int32_t gauss_n;     // error integral: 0 adaptive tanh-sinh, n > 0 the n-point Gauss-Legendre rule
 };
 
 // Intermediate-time sampling (second remark after Alg. 1): the step kernel computes the Krylov

@@ -38,7 +38,8 @@ class te_c128(ctypes.Structure):
 class te_options(ctypes.Structure):
     _fields_ = [("n_substeps", ctypes.c_int32), ("t_init", ctypes.c_double), ("shrink", ctypes.c_double),
                 ("quad_rel_tol", ctypes.c_double), ("quad_max_level", ctypes.c_int32),
-                ("quad_min_level", ctypes.c_int32), ("max_halvings", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+                ("quad_min_level", ctypes.c_int32), ("max_halvings", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("quad_gauss_points", ctypes.c_int32)]
 
 
 class te_result(ctypes.Structure):

@@ -37,7 +37,7 @@ def test_host_only_calls():
     from paper_2205_15346_amd import te
     o = te.te_default_options()
     assert (o.n_substeps, o.t_init, o.shrink, o.quad_rel_tol, o.quad_max_level, o.quad_min_level,
-            o.max_halvings, o.flags) == (10, 0.1, 0.97, 1e-3, 15, 3, 64, 0)
+            o.max_halvings, o.flags, o.quad_gauss_points) == (10, 0.1, 0.97, 1e-3, 15, 3, 64, 0, 0)
     assert te.te_status_string(te.TE_OK) == "ok"
     assert "step" in te.te_status_string(te.TE_ERR_STEP_UNDERFLOW)
     # workspace: 40 basis columns + work vector of 2^20 complex numbers, plus small scratch
