@@ -81,14 +81,22 @@ __device__ bool tridiag_ql(int k, const double* a, const double* b, double* lam,
             double carry = Qt[mm * 64 + lane];
             int i = mm - 1;
             int underflow = 0;
+            // operands of the next rotation are fetched one step ahead (all pre-sweep values)
+            double ei_n = lane_get(er, i), di_n = lane_get(dr, i), di1_n = lane_get(dr, i + 1);
+            double qi_n = Qt[i * 64 + lane];
             for (; i >= l; --i) {
-                const double ei = lane_get(er, i), di = lane_get(dr, i), di1 = lane_get(dr, i + 1);
-                const double qi = Qt[i * 64 + lane];
+                const double ei = ei_n, di = di_n, di1 = di1_n, qi = qi_n;
+                if (i > l) {
+                    ei_n = lane_get(er, i - 1);
+                    di1_n = di;
+                    di_n = lane_get(dr, i - 1);
+                    qi_n = Qt[(i - 1) * 64 + lane];
+                }
                 const double f = s * ei;
                 const double bb = c * ei;
                 const double t = fma(f, f, g * g);
-                // wave-uniform test as a scalar branch
-                if (__builtin_amdgcn_readfirstlane((int)(t == 0.0))) {
+                // wave-uniform test: the compare mask itself drives a scalar branch
+                if (__builtin_amdgcn_ballot_w64(t == 0.0) != 0) {
                     if (lane == i + 1) dr = di1 - p;
                     if (lane == mm) er = 0.0;
                     underflow = 1;
