@@ -212,7 +212,7 @@ te_status te_last_profile(te_hamiltonian h, te_profile* out);
 typedef struct {
     int32_t lanes_per_row;          /* lanes sharing one row of the sparse product: 4 or 8 */
     int32_t nnz_per_lane;           /* nonzeros per lane in flight: 1 or 4 (4 lanes), 2 (8 lanes) */
-    int32_t rows_per_thread;        /* projection kernel: 1 or 2 */
+    int32_t rows_per_thread;        /* projection kernel: 1, 2 or 4 (4: batches of 4 columns) */
     int32_t update_rows_per_thread; /* update and recombination kernels: 1 or 2 */
     int32_t split_projection;       /* 0: sparse product fused with the projections in one kernel;
                                        1: two launches, the product vector read back (same results) */
@@ -310,7 +310,7 @@ typedef struct {
     uint64_t hbm_budget;            /* bytes of device memory for job workspaces, allocated once */
     int32_t lanes_per_row;          /* sparse-product shape: 4 or 8 lanes per row; 0 = autotune */
     int32_t nnz_per_lane;           /* 1 or 4 with 4 lanes, 2 with 8 lanes */
-    int32_t rows_per_thread;        /* projections: 1 or 2 rows per thread; 0 = 2 */
+    int32_t rows_per_thread;        /* projections: 1, 2 or 4 rows per thread; 0 = 4 */
     int32_t update_rows_per_thread; /* update and recombination: 1 or 2; 0 = 2 */
     uint32_t flags;                 /* TE_ENGINE_* */
     te_options opt;                 /* step-size / quadrature options; opt.flags: 0 or TE_OPT_LANCZOS3 */

@@ -362,7 +362,7 @@ te_status run_autotune(te_hamiltonian h, Workspace* w, hipStream_t s) {
     double best_us = 1e30;
     hipError_t err = hipSuccess;
     for (int sp = 0; sp <= 1 && err == hipSuccess; ++sp)
-    for (int rp = 1; rp <= 2 && err == hipSuccess; ++rp) {
+    for (int rp = 1; rp <= 4 && err == hipSuccess; rp *= 2) {
         for (const auto& sh : shapes) {
             const Tiling t = make_tiling(w->dim, rp, sh[0], sh[1], rpt_u, sp);
             RedBuf rb = w->rb;

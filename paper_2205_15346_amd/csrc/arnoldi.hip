@@ -28,7 +28,7 @@ int max_tiles(int dim) { return (dim + kBlock - 1) / kBlock; }
 
 bool tiling_supported(int rpt_p, int g, int u, int rpt_u, int split) {
     const bool shape = (g == 4 && (u == 1 || u == 4)) || (g == 8 && u == 2);
-    return shape && (rpt_p == 1 || rpt_p == 2) && (rpt_u == 1 || rpt_u == 2) && (split == 0 || split == 1);
+    return shape && (rpt_p == 1 || rpt_p == 2 || rpt_p == 4) && (rpt_u == 1 || rpt_u == 2) && (split == 0 || split == 1);
 }
 
 Tiling make_tiling(int dim, int rpt_p, int g, int u, int rpt_u, int split) {
@@ -123,8 +123,8 @@ constexpr int kDppQuadXor2 = 0x4E;        // quad_perm [2, 3, 0, 1]
 constexpr int kDppQuadXor1 = 0xB1;        // quad_perm [1, 0, 3, 2]
 
 // H values move; BIT of the lane id decides which half is kept; EX selects the exchange
-template <int H, int BIT, int EX>
-__device__ __forceinline__ void halve(double (&a)[32], int lane) {
+template <int N, int H, int BIT, int EX>
+__device__ __forceinline__ void halve(double (&a)[N], int lane) {
     const bool hi = ((lane >> BIT) & 1) != 0;
 #pragma unroll
     for (int v = 0; v < H; ++v) {
@@ -142,17 +142,33 @@ __device__ __forceinline__ void halve(double (&a)[32], int lane) {
 
 // Returns, in every lane, the full sum of value halving_value(lane & 31).
 __device__ __forceinline__ double halving_reduce32(double (&a)[32], int lane) {
-    halve<16, 3, 0>(a, lane);
-    halve<8, 2, 1>(a, lane);
-    halve<4, 1, 2>(a, lane);
-    halve<2, 0, 3>(a, lane);
-    halve<1, 4, 4>(a, lane);
+    halve<32, 16, 3, 0>(a, lane);
+    halve<32, 8, 2, 1>(a, lane);
+    halve<32, 4, 1, 2>(a, lane);
+    halve<32, 2, 0, 3>(a, lane);
+    halve<32, 1, 4, 4>(a, lane);
     return a[0] + __shfl_xor(a[0], 32);
 }
 
 // index (0..31) of the value whose sum lanes l and l + 32 hold after halving_reduce32
 __device__ __forceinline__ int halving_value(int lane) {
     return ((lane >> 3) & 1) * 16 + ((lane >> 2) & 1) * 8 + ((lane >> 1) & 1) * 4 + (lane & 1) * 2 + ((lane >> 4) & 1);
+}
+
+// The same for 16 values (4 columns): four DPP halvings inside each row of 16 lanes, then the
+// rows are added pairwise (lane ^ 16, lane ^ 32).  Every lane returns the full sum of value
+// halving_value16(lane & 15).
+__device__ __forceinline__ double halving_reduce16(double (&a)[16], int lane) {
+    halve<16, 8, 3, 0>(a, lane);
+    halve<16, 4, 2, 1>(a, lane);
+    halve<16, 2, 1, 2>(a, lane);
+    halve<16, 1, 0, 3>(a, lane);
+    const double v = a[0] + swizzle_xor16(a[0]);
+    return v + __shfl_xor(v, 32);
+}
+
+__device__ __forceinline__ int halving_value16(int lane) {
+    return ((lane >> 3) & 1) * 8 + ((lane >> 2) & 1) * 4 + ((lane >> 1) & 1) * 2 + (lane & 1);
 }
 
 // y = H V[:, j] (raw) on rows [r0, r1): G lanes per row stream the CSR, each with U nonzeros
@@ -228,12 +244,15 @@ __device__ __forceinline__ void project_body(const int* __restrict__ rp, const i
             xq[q] = make_double2(0.0, 0.0);
         }
     }
-    // projections on columns i_lo..j in batches of 8 (i_lo = j - 1 in three-term mode)
+    // projections on columns i_lo..j (i_lo = j - 1 in three-term mode) in batches of CB: with
+    // four rows per thread, batches of 4 keep the loads of a batch in flight without spilling
+    // the occupancy below four waves per SIMD
+    constexpr int CB = RPT >= 4 ? 4 : 8;
     const int i_lo = (st->p.three_term && j >= 1) ? j - 1 : 0;
-    for (int i0 = i_lo; i0 <= j; i0 += 8) {
-        double a[32];
+    for (int i0 = i_lo; i0 <= j; i0 += CB) {
+        double a[4 * CB];
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
+        for (int b = 0; b < CB; ++b) {
             double2 cy = make_double2(0.0, 0.0), cx = make_double2(0.0, 0.0);
             const int i = i0 + b;
             if (i <= j) {
@@ -253,9 +272,16 @@ __device__ __forceinline__ void project_body(const int* __restrict__ rp, const i
             a[4 * b + 2] = cx.x;
             a[4 * b + 3] = cx.y;
         }
-        const double s = halving_reduce32(a, lane);
-        if (lane < 32) {
-            const int v = halving_value(lane);  // 4 * column-in-batch + component
+        double s;
+        int v;  // 4 * column-in-batch + component
+        if constexpr (CB == 8) {
+            s = halving_reduce32(a, lane);
+            v = halving_value(lane);
+        } else {
+            s = halving_reduce16(a, lane);
+            v = halving_value16(lane);
+        }
+        if (lane < 4 * CB) {
             const int i = i0 + (v >> 2);
             if (i <= j) {
                 double* dst = (double*)&wpart[wave][2 * i + ((v >> 1) & 1)];
@@ -849,6 +875,15 @@ static hipError_t by_rpt(int rpt, F&& f) {
     return hipGetLastError();
 }
 
+// the projections also come with four rows per thread
+template <typename F>
+static hipError_t by_rpt_p(int rpt, F&& f) {
+    if (rpt == 1) f(std::integral_constant<int, 1>{});
+    else if (rpt == 2) f(std::integral_constant<int, 2>{});
+    else f(std::integral_constant<int, 4>{});
+    return hipGetLastError();
+}
+
 static int grid_for(int dim) { return (int)std::min<int64_t>(((int64_t)dim + kBlock - 1) / kBlock, 4096); }
 
 // ----------------------------------------------------------------- batched launchers
@@ -871,7 +906,7 @@ hipError_t launch_gproject(int g, int u, int rpt, int nv_class, const JobView* j
                            const int2* items, int n_items, int j, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
     const dim3 grid(n_items);
-    return by_rpt(rpt, [&](auto r) {
+    return by_rpt_p(rpt, [&](auto r) {
         constexpr int RPT = decltype(r)::value;
         if (g == 8) gproject_nv<RPT, 8, 2>(nv_class, grid, s, jobs, groups, items, j);
         else if (u == 1) gproject_nv<RPT, 4, 1>(nv_class, grid, s, jobs, groups, items, j);
@@ -881,7 +916,7 @@ hipError_t launch_gproject(int g, int u, int rpt, int nv_class, const JobView* j
 
 hipError_t launch_bdots(int rpt, const JobView* jobs, const int2* items, int n_items, int j, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
-    return by_rpt(rpt, [&](auto r) { k_bdots<decltype(r)::value><<<n_items, kBlock, 0, s>>>(jobs, items, j); });
+    return by_rpt_p(rpt, [&](auto r) { k_bdots<decltype(r)::value><<<n_items, kBlock, 0, s>>>(jobs, items, j); });
 }
 
 hipError_t launch_bfold(const JobView* jobs, int n_jobs, int j, hipStream_t s) {
@@ -936,7 +971,7 @@ hipError_t launch_copy(const double2* src, double2* dst, int dim, hipStream_t s)
 
 hipError_t launch_project(const Tiling& tl, const Csr& H, const double2* V, int64_t ld, int j, double2* y,
                           const DevState* st, const RedBuf& rb, hipStream_t s) {
-    return by_rpt(tl.rpt_p, [&](auto r) {
+    return by_rpt_p(tl.rpt_p, [&](auto r) {
         constexpr int RPT = decltype(r)::value;
         const dim3 grid(tl.n_tiles_p), block(kBlock);
         if (tl.split) {  // the sparse product keeps one row per thread; rpt_p shapes the projections

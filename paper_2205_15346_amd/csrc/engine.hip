@@ -731,9 +731,10 @@ te_status check_config(const te_engine_config& c) {
     if (c.max_jobs < 1 || c.max_jobs > kMaxEngineJobs) return set_error(TE_ERR_INVALID_ARG, "max_jobs out of range");
     if (c.lanes_per_row != 0 && !gproject_supported(c.lanes_per_row, c.nnz_per_lane))
         return set_error(TE_ERR_INVALID_ARG, "unsupported projection shape (4 lanes with 1 or 4 nonzeros, 8 with 2)");
-    if (c.update_rows_per_thread < 0 || c.update_rows_per_thread > 2 || c.rows_per_thread < 0 ||
-        c.rows_per_thread > 2)
-        return set_error(TE_ERR_INVALID_ARG, "rows_per_thread and update_rows_per_thread must be 0, 1 or 2");
+    if (c.update_rows_per_thread < 0 || c.update_rows_per_thread > 2)
+        return set_error(TE_ERR_INVALID_ARG, "update_rows_per_thread must be 0, 1 or 2");
+    if (c.rows_per_thread != 0 && c.rows_per_thread != 1 && c.rows_per_thread != 2 && c.rows_per_thread != 4)
+        return set_error(TE_ERR_INVALID_ARG, "rows_per_thread must be 0, 1, 2 or 4");
     if (c.flags & ~(TE_ENGINE_THREADED | TE_ENGINE_PROFILE)) return set_error(TE_ERR_INVALID_ARG, "unknown flags");
     if (c.opt.flags & ~TE_OPT_LANCZOS3)
         return set_error(TE_ERR_INVALID_ARG, "engine options take only TE_OPT_LANCZOS3 (profiling: TE_ENGINE_PROFILE)");
@@ -797,7 +798,7 @@ te_status te_engine_create(te_engine* out, const te_engine_config* cfg, void* st
         e->tuning.nnz_per_lane = cfg->nnz_per_lane;
         e->tuned = true;
     }
-    e->tuning.rows_per_thread = cfg->rows_per_thread ? cfg->rows_per_thread : 2;
+    e->tuning.rows_per_thread = cfg->rows_per_thread ? cfg->rows_per_thread : 4;
     e->tuning.update_rows_per_thread = cfg->update_rows_per_thread ? cfg->update_rows_per_thread : 2;
     auto chk = [&](hipError_t r, const char* what) {
         if (r != hipSuccess && rc == TE_OK) rc = hip_fail(r, what);

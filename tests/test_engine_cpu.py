@@ -65,7 +65,7 @@ def test_default_config():
 @pytest.mark.parametrize("field,value,status", [
     ("m", 1, "TE_ERR_INVALID_ARG"), ("m", 65, "TE_ERR_UNSUPPORTED"), ("max_jobs", 0, "TE_ERR_INVALID_ARG"),
     ("max_jobs", 16385, "TE_ERR_INVALID_ARG"), ("lanes_per_row", 3, "TE_ERR_INVALID_ARG"),
-    ("update_rows_per_thread", 3, "TE_ERR_INVALID_ARG"), ("rows_per_thread", 4, "TE_ERR_INVALID_ARG"),
+    ("update_rows_per_thread", 3, "TE_ERR_INVALID_ARG"), ("rows_per_thread", 3, "TE_ERR_INVALID_ARG"),
     ("flags", 8, "TE_ERR_INVALID_ARG"),
     ("hbm_budget", 0, "TE_ERR_INVALID_ARG")])
 def test_engine_create_validates_before_touching_the_device(field, value, status):

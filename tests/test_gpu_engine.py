@@ -52,7 +52,7 @@ def mixed_groups():
     return groups
 
 
-@pytest.mark.parametrize("tune", [((4, 4), 2, 2), ((8, 2), 1, 1), ((4, 1), 2, 1)])
+@pytest.mark.parametrize("tune", [((4, 4), 2, 2), ((8, 2), 1, 1), ((4, 1), 2, 1), ((8, 2), 4, 2)])
 def test_batch_bitwise_equals_alone(mixed_groups, tune):
     te = lib()
     shape, rpt, rpt_u = tune

@@ -57,12 +57,14 @@ def test_three_term_kernel_shapes_agree_bitwise():
     outs = []
     with hamiltonian(H) as h:
         x = to_dev(v0)
-        for shape in [(4, 4, 1, 1, 0), (4, 4, 1, 1, 1), (8, 2, 2, 2, 0), (8, 2, 2, 2, 1)]:
+        for shape in [(4, 4, 1, 1, 0), (4, 4, 1, 1, 1), (8, 2, 2, 2, 0), (8, 2, 2, 2, 1), (8, 2, 4, 2, 0),
+                      (8, 2, 4, 2, 1)]:
             te.te_set_tuning(h, *shape)
             v, res = te.te_evolve(h, x, 6.0, 1e-8, 40, options=opts3(te))
             outs.append((shape, to_host(v), res.steps))
     # split and fused forms of one shape are bitwise equal; other shapes within the bounds
     assert np.array_equal(outs[0][1], outs[1][1]) and np.array_equal(outs[2][1], outs[3][1])
+    assert np.array_equal(outs[4][1], outs[5][1])
     assert np.linalg.norm(outs[0][1] - outs[2][1]) <= 2e-8 + 1e-12
 
 
