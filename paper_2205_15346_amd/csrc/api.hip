@@ -129,6 +129,7 @@ te_hamiltonian_s::~te_hamiltonian_s() {
     dev_free(row_ptr);
     dev_free(col);
     dev_free(val);
+    dev_free(rval);
 }
 
 namespace {
@@ -237,7 +238,7 @@ hipError_t accumulate_profile(te_hamiltonian h, Workspace* w, std::vector<hipEve
         p->seconds[TE_KERNEL_PROJECT] += t;
         // CSR (values, columns, row pointers), columns i_lo..j of V, y written
         const int cols = (three_term && j >= 1) ? 2 : j + 1;
-        p->bytes[TE_KERNEL_PROJECT] += 20.0 * nnz + 4.0 * (d + 1) + 16.0 * d * (cols + 1);
+        p->bytes[TE_KERNEL_PROJECT] += csr_entry_bytes(h->csr) * nnz + 4.0 * (d + 1) + 16.0 * d * (cols + 1);
         e = span(3 * j + 1, 3 * j + 2, &t);
         if (e != hipSuccess) return e;
         p->launches[TE_KERNEL_FOLD] += 1;
@@ -502,7 +503,7 @@ te_status te_hamiltonian_create(te_hamiltonian* out, int64_t dim, int64_t nnz, c
     *out = nullptr;
     if (dim < 1 || dim >= ((int64_t)1 << 31) - 1) return fail(TE_ERR_INVALID_ARG, "dim out of range");
     if (nnz < 1 || nnz >= ((int64_t)1 << 31)) return fail(TE_ERR_INVALID_CSR, "nnz out of range (1..2^31-1)");
-    if (flags & ~(TE_PTR_DEVICE | TE_CHECK_HERMITIAN)) return fail(TE_ERR_INVALID_ARG, "unknown flags");
+    if (flags & ~(TE_PTR_DEVICE | TE_CHECK_HERMITIAN | TE_STORE_COMPLEX)) return fail(TE_ERR_INVALID_ARG, "unknown flags");
     hipStream_t s = (hipStream_t)stream;
     auto* h = new (std::nothrow) te_hamiltonian_s();
     if (!h) return fail(TE_ERR_OUT_OF_MEMORY, "host allocation failed");
@@ -533,6 +534,7 @@ te_status te_hamiltonian_create(te_hamiltonian* out, int64_t dim, int64_t nnz, c
     h->csr.row_ptr = h->row_ptr;
     h->csr.col = h->col;
     h->csr.val = h->val;
+    h->csr.rval = nullptr;
     h->csr.dim = (int)dim;
     h->csr.nnz = nnz;
     if (rc == TE_OK) chk(launch_validate(h->csr, (flags & TE_CHECK_HERMITIAN) ? 1 : 0, err, rowsum, s), "validate");
@@ -546,6 +548,19 @@ te_status te_hamiltonian_create(te_hamiltonian* out, int64_t dim, int64_t nnz, c
         rc = fail(TE_ERR_INVALID_CSR, "invalid CSR (code " + std::to_string(herr) + ": 1 structure, 2 column range, "
                                       "4 non-finite value, 8 unsorted columns)");
     if (rc == TE_OK && (herr & 16)) rc = fail(TE_ERR_NOT_HERMITIAN, "H differs from its conjugate transpose");
+    if (rc == TE_OK && !(herr & 32) && !(flags & TE_STORE_COMPLEX)) {
+        // every imaginary part is zero: keep the real parts only
+        h->rval = (double*)dev_alloc(nnz * sizeof(double));
+        if (!h->rval) rc = fail(TE_ERR_OUT_OF_MEMORY, "device allocation for the real entries failed");
+        if (rc == TE_OK) chk(launch_real_part(h->val, h->rval, nnz, s), "real part");
+        if (rc == TE_OK) chk(hipStreamSynchronize(s), "hipStreamSynchronize");
+        if (rc == TE_OK) {
+            dev_free(h->val);
+            h->val = nullptr;
+            h->csr.val = nullptr;
+            h->csr.rval = h->rval;
+        }
+    }
     if (rc != TE_OK) {
         delete h;
         return rc;
@@ -559,6 +574,12 @@ te_status te_hamiltonian_destroy(te_hamiltonian h) {
     if (!h) return fail(TE_ERR_INVALID_ARG, "null handle");
     (void)hipDeviceSynchronize();
     delete h;
+    return TE_OK;
+}
+
+te_status te_hamiltonian_real_values(te_hamiltonian h, int32_t* real_values) {
+    if (!h || !real_values) return fail(TE_ERR_INVALID_ARG, "null pointer");
+    *real_values = h->csr.rval ? 1 : 0;
     return TE_OK;
 }
 

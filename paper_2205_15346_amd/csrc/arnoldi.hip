@@ -171,19 +171,35 @@ __device__ __forceinline__ int halving_value16(int lane) {
     return ((lane >> 3) & 1) * 8 + ((lane >> 2) & 1) * 4 + ((lane >> 1) & 1) * 2 + (lane & 1);
 }
 
+// One stored entry times an entry of x, added to acc: complex entries, or real ones (a matrix
+// whose imaginary parts are all zero is stored with 8-byte entries; the products are the same
+// values, since the imaginary part would only add exact zeros).
+__device__ __forceinline__ double2 entry_fma(double2 v, double2 x, double2 acc) { return cfma(v, x, acc); }
+__device__ __forceinline__ double2 entry_fma(double v, double2 x, double2 acc) {
+    acc.x = fma(v, x.x, acc.x);
+    acc.y = fma(v, x.y, acc.y);
+    return acc;
+}
+template <typename VT>
+__device__ __forceinline__ VT entry_zero();
+template <>
+__device__ __forceinline__ double2 entry_zero<double2>() { return make_double2(0.0, 0.0); }
+template <>
+__device__ __forceinline__ double entry_zero<double>() { return 0.0; }
+
 // y = H V[:, j] (raw) on rows [r0, r1): G lanes per row stream the CSR, each with U nonzeros
 // in flight; results to y and, if ytile is given, to LDS.
-template <int G, int U>
-__device__ __forceinline__ void tile_spmv(const int* __restrict__ rp, const int* __restrict__ ci,
-                                          const double2* __restrict__ val, const double2* __restrict__ x,
-                                          int r0, int r1, double2* __restrict__ y, double2* ytile) {
+template <int G, int U, typename VT>
+__device__ __forceinline__ void tile_spmv_t(const int* __restrict__ rp, const int* __restrict__ ci,
+                                            const VT* __restrict__ val, const double2* __restrict__ x,
+                                            int r0, int r1, double2* __restrict__ y, double2* ytile) {
     const int tid = threadIdx.x;
     const int lg = tid % G, grp = tid / G;
     for (int r = r0 + grp; r < r1; r += kBlock / G) {
         double2 acc = make_double2(0.0, 0.0);
         const int kb = rp[r], ke = rp[r + 1];
         for (int k0 = kb + lg; k0 < ke; k0 += G * U) {
-            double2 vv[U];
+            VT vv[U];
             int cc[U];
 #pragma unroll
             for (int q = 0; q < U; ++q) {
@@ -192,13 +208,13 @@ __device__ __forceinline__ void tile_spmv(const int* __restrict__ rp, const int*
                     vv[q] = val[k];
                     cc[q] = ci[k];
                 } else {
-                    vv[q] = make_double2(0.0, 0.0);
+                    vv[q] = entry_zero<VT>();
                     cc[q] = -1;
                 }
             }
 #pragma unroll
             for (int q = 0; q < U; ++q)
-                if (cc[q] >= 0) acc = cfma(vv[q], x[cc[q]], acc);
+                if (cc[q] >= 0) acc = entry_fma(vv[q], x[cc[q]], acc);
         }
 #pragma unroll
         for (int o = G / 2; o > 0; o >>= 1) {
@@ -212,11 +228,21 @@ __device__ __forceinline__ void tile_spmv(const int* __restrict__ rp, const int*
     }
 }
 
+template <int G, int U>
+__device__ __forceinline__ void tile_spmv(const int* __restrict__ rp, const int* __restrict__ ci,
+                                          const double2* __restrict__ val, const double* __restrict__ rval,
+                                          const double2* __restrict__ x, int r0, int r1, double2* __restrict__ y,
+                                          double2* ytile) {
+    if (rval) tile_spmv_t<G, U, double>(rp, ci, rval, x, r0, r1, y, ytile);
+    else tile_spmv_t<G, U, double2>(rp, ci, val, x, r0, r1, y, ytile);
+}
+
 // Projection of iteration j on one tile.  FROM_Y: the sparse product already ran (k_yspmv)
 // and y is read back; otherwise it is computed here and kept in LDS.
 template <int RPT, int G, int U, bool FROM_Y>
 __device__ __forceinline__ void project_body(const int* __restrict__ rp, const int* __restrict__ ci,
-                                             const double2* __restrict__ val, const double2* __restrict__ V,
+                                             const double2* __restrict__ val, const double* __restrict__ rval,
+                                             const double2* __restrict__ V,
                                              int64_t ld, int dim, int j, double2* __restrict__ y,
                                              const DevState* __restrict__ st, const RedBuf& rb, int tile) {
     constexpr int R = kBlock * RPT;
@@ -229,7 +255,7 @@ __device__ __forceinline__ void project_body(const int* __restrict__ rp, const i
     const double2* __restrict__ x = V + (int64_t)j * ld;
 
     if (!FROM_Y) {
-        tile_spmv<G, U>(rp, ci, val, x, r0, r1, y, ytile);
+        tile_spmv<G, U>(rp, ci, val, rval, x, r0, r1, y, ytile);
         __syncthreads();
     }
     double2 yq[RPT], xq[RPT];
@@ -300,21 +326,22 @@ __device__ __forceinline__ void project_body(const int* __restrict__ rp, const i
 
 template <int RPT, int G, int U, bool FROM_Y>
 __global__ __launch_bounds__(kBlock) void k_project(const int* __restrict__ rp, const int* __restrict__ ci,
-                                                     const double2* __restrict__ val, const double2* __restrict__ V,
-                                                     int64_t ld, int dim, int j, double2* __restrict__ y,
-                                                     const DevState* __restrict__ st, RedBuf rb) {
-    project_body<RPT, G, U, FROM_Y>(rp, ci, val, V, ld, dim, j, y, st, rb, blockIdx.x);
+                                                     const double2* __restrict__ val, const double* __restrict__ rval,
+                                                     const double2* __restrict__ V, int64_t ld, int dim, int j,
+                                                     double2* __restrict__ y, const DevState* __restrict__ st,
+                                                     RedBuf rb) {
+    project_body<RPT, G, U, FROM_Y>(rp, ci, val, rval, V, ld, dim, j, y, st, rb, blockIdx.x);
 }
 
 // sparse product alone (split projection): y = H V[:, j] on the rows of one projection tile
 template <int RPT, int G, int U>
 __global__ __launch_bounds__(kBlock) void k_yspmv(const int* __restrict__ rp, const int* __restrict__ ci,
-                                                   const double2* __restrict__ val, const double2* __restrict__ V,
-                                                   int64_t ld, int dim, int j, double2* __restrict__ y,
-                                                   const DevState* __restrict__ st) {
+                                                   const double2* __restrict__ val, const double* __restrict__ rval,
+                                                   const double2* __restrict__ V, int64_t ld, int dim, int j,
+                                                   double2* __restrict__ y, const DevState* __restrict__ st) {
     if (st->done || j >= st->k_limit) return;
     const int r0 = blockIdx.x * kBlock * RPT;
-    tile_spmv<G, U>(rp, ci, val, V + (int64_t)j * ld, r0, min(r0 + kBlock * RPT, dim), y, nullptr);
+    tile_spmv<G, U>(rp, ci, val, rval, V + (int64_t)j * ld, r0, min(r0 + kBlock * RPT, dim), y, nullptr);
 }
 
 // Batched projection.  Jobs that share H form a group; a group of one runs the fused kernel
@@ -348,13 +375,12 @@ __device__ __forceinline__ unsigned group_mask(const JobView* __restrict__ jobs,
 
 // y_v = H V_v[:, j] on rows [r0, r1) for every live vector: G lanes per row, U nonzeros in
 // flight each; results to y_v and, if ytile is given, to LDS (NV = 1).
-template <int G, int U, int NV>
-__device__ __forceinline__ void group_spmv(const GroupView& gv, int r0, int r1, unsigned mask,
-                                           const double2* const (&xs)[NV], double2* const (&ys)[NV],
-                                           double2* ytile) {
+template <int G, int U, int NV, typename VT>
+__device__ __forceinline__ void group_spmv(const GroupView& gv, const VT* __restrict__ val, int r0, int r1,
+                                           unsigned mask, const double2* const (&xs)[NV],
+                                           double2* const (&ys)[NV], double2* ytile) {
     const int* __restrict__ rp = gv.rp;
     const int* __restrict__ ci = gv.ci;
-    const double2* __restrict__ val = gv.val;
     const int tid = threadIdx.x;
     const int lg = tid % G, grp = tid / G;
     for (int r = r0 + grp; r < r1; r += kBlock / G) {
@@ -363,7 +389,7 @@ __device__ __forceinline__ void group_spmv(const GroupView& gv, int r0, int r1, 
         for (int v = 0; v < NV; ++v) acc[v] = make_double2(0.0, 0.0);
         const int kb = rp[r], ke = rp[r + 1];
         for (int k0 = kb + lg; k0 < ke; k0 += G * U) {
-            double2 vv[U];
+            VT vv[U];
             int cc[U];
 #pragma unroll
             for (int q = 0; q < U; ++q) {
@@ -372,7 +398,7 @@ __device__ __forceinline__ void group_spmv(const GroupView& gv, int r0, int r1, 
                     vv[q] = val[k];
                     cc[q] = ci[k];
                 } else {
-                    vv[q] = make_double2(0.0, 0.0);
+                    vv[q] = entry_zero<VT>();
                     cc[q] = -1;
                 }
             }
@@ -381,7 +407,7 @@ __device__ __forceinline__ void group_spmv(const GroupView& gv, int r0, int r1, 
                 if (cc[q] < 0) continue;
 #pragma unroll
                 for (int v = 0; v < NV; ++v)
-                    if (mask & (1u << v)) acc[v] = cfma(vv[q], xs[v][cc[q]], acc[v]);
+                    if (mask & (1u << v)) acc[v] = entry_fma(vv[q], xs[v][cc[q]], acc[v]);
             }
         }
 #pragma unroll
@@ -406,7 +432,7 @@ __global__ __launch_bounds__(kBlock) void k_gproject(const JobView* __restrict__
                                                       const int2* __restrict__ items, int j) {
     const int2 it = items[blockIdx.x];
     const JobView& J = jobs[groups[it.x].job[0]];
-    project_body<RPT, G, U, false>(J.rp, J.ci, J.val, J.V, J.ld, J.dim, j, J.y, J.st, J.rb, it.y);
+    project_body<RPT, G, U, false>(J.rp, J.ci, J.val, J.rval, J.V, J.ld, J.dim, j, J.y, J.st, J.rb, it.y);
 }
 
 // multi-vector sparse product of a group: one workgroup per (group, tile)
@@ -421,7 +447,8 @@ __global__ __launch_bounds__(kBlock) void k_gspmm(const JobView* __restrict__ jo
     const unsigned mask = group_mask<NV>(jobs, gv, j, xs, ys);
     if (mask == 0) return;
     const int r0 = it.y * kBlock;
-    group_spmv<G, U, NV>(gv, r0, min(r0 + kBlock, gv.dim), mask, xs, ys, nullptr);
+    if (gv.rval) group_spmv<G, U, NV, double>(gv, gv.rval, r0, min(r0 + kBlock, gv.dim), mask, xs, ys, nullptr);
+    else group_spmv<G, U, NV, double2>(gv, gv.val, r0, min(r0 + kBlock, gv.dim), mask, xs, ys, nullptr);
 }
 
 // projections after a multi-vector product: one workgroup per (job, tile of kBlock * RPT rows)
@@ -430,7 +457,7 @@ __global__ __launch_bounds__(kBlock) void k_bdots(const JobView* __restrict__ jo
                                                   int j) {
     const int2 it = items[blockIdx.x];
     const JobView& J = jobs[it.x];
-    project_body<RPT, 4, 4, true>(J.rp, J.ci, J.val, J.V, J.ld, J.dim, j, J.y, J.st, J.rb, it.y);
+    project_body<RPT, 4, 4, true>(J.rp, J.ci, J.val, J.rval, J.V, J.ld, J.dim, j, J.y, J.st, J.rb, it.y);
 }
 
 // ---------------------------------------------------- fold of the projection partials
@@ -761,9 +788,9 @@ __global__ __launch_bounds__(kBlock) void k_output(const double2* __restrict__ V
 }
 
 // ---------------------------------------------------------- standalone sparse product
-template <int G>
+template <int G, typename VT>
 __global__ __launch_bounds__(kBlock) void k_spmv(const int* __restrict__ rp, const int* __restrict__ ci,
-                                                  const double2* __restrict__ val, const double2* __restrict__ x,
+                                                  const VT* __restrict__ val, const double2* __restrict__ x,
                                                   double2* __restrict__ y, int dim, RedBuf rb, int rows_per_tile) {
     __shared__ double lds[kWaves];
     const int tid = threadIdx.x, lg = tid % G, grp = tid / G;
@@ -772,7 +799,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(const int* __restrict__ rp, con
     double2 dot = make_double2(0.0, 0.0);
     for (int r = r0 + grp; r < r1; r += kBlock / G) {
         double2 acc = make_double2(0.0, 0.0);
-        for (int k = rp[r] + lg; k < rp[r + 1]; k += G) acc = cfma(val[k], x[ci[k]], acc);
+        for (int k = rp[r] + lg; k < rp[r + 1]; k += G) acc = entry_fma(val[k], x[ci[k]], acc);
 #pragma unroll
         for (int o = G / 2; o > 0; o >>= 1) {
             acc.x += __shfl_xor(acc.x, o);
@@ -799,7 +826,8 @@ __global__ __launch_bounds__(kBlock) void k_sum_part(DevState* st, RedBuf rb) {
 }
 
 // ------------------------------------------------------------------ CSR validation
-// err bits: 1 structure, 2 column range, 4 non-finite, 8 unsorted (Hermitian check), 16 not Hermitian
+// err bits: 1 structure, 2 column range, 4 non-finite, 8 unsorted (Hermitian check), 16 not Hermitian;
+// bit 32 (not an error) marks a nonzero imaginary part
 __global__ __launch_bounds__(kBlock) void k_validate(const int* __restrict__ rp, const int* __restrict__ ci,
                                                       const double2* __restrict__ val, int dim, int64_t nnz,
                                                       int check_herm, int* err, double* rowsum) {
@@ -823,6 +851,7 @@ __global__ __launch_bounds__(kBlock) void k_validate(const int* __restrict__ rp,
             continue;
         }
         if (!isfinite(v.x) || !isfinite(v.y)) e |= 4;
+        if (v.y != 0.0) e |= 32;
         sum += hypot(v.x, v.y);
         if (check_herm) {
             if (k > kb && ci[k - 1] >= c) e |= 8;
@@ -850,6 +879,12 @@ __global__ __launch_bounds__(kBlock) void k_validate(const int* __restrict__ rp,
     }
     rowsum[r] = sum;
     if (e) atomicOr(err, e);
+}
+
+__global__ __launch_bounds__(kBlock) void k_real_part(const double2* __restrict__ val, double* __restrict__ rval,
+                                                       int64_t n) {
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < n; k += (int64_t)gridDim.x * kBlock)
+        rval[k] = val[k].x;
 }
 
 __global__ __launch_bounds__(kBlock) void k_max(const double* __restrict__ a, int n, double* out) {
@@ -976,14 +1011,14 @@ hipError_t launch_project(const Tiling& tl, const Csr& H, const double2* V, int6
         const dim3 grid(tl.n_tiles_p), block(kBlock);
         if (tl.split) {  // the sparse product keeps one row per thread; rpt_p shapes the projections
             const dim3 g1((H.dim + kBlock - 1) / kBlock);
-            if (tl.g == 8) k_yspmv<1, 8, 2><<<g1, block, 0, s>>>(H.row_ptr, H.col, H.val, V, ld, H.dim, j, y, st);
-            else if (tl.u == 1) k_yspmv<1, 4, 1><<<g1, block, 0, s>>>(H.row_ptr, H.col, H.val, V, ld, H.dim, j, y, st);
-            else k_yspmv<1, 4, 4><<<g1, block, 0, s>>>(H.row_ptr, H.col, H.val, V, ld, H.dim, j, y, st);
-            k_project<RPT, 4, 4, true><<<grid, block, 0, s>>>(H.row_ptr, H.col, H.val, V, ld, H.dim, j, y, st, rb);
+            if (tl.g == 8) k_yspmv<1, 8, 2><<<g1, block, 0, s>>>(H.row_ptr, H.col, H.val, H.rval, V, ld, H.dim, j, y, st);
+            else if (tl.u == 1) k_yspmv<1, 4, 1><<<g1, block, 0, s>>>(H.row_ptr, H.col, H.val, H.rval, V, ld, H.dim, j, y, st);
+            else k_yspmv<1, 4, 4><<<g1, block, 0, s>>>(H.row_ptr, H.col, H.val, H.rval, V, ld, H.dim, j, y, st);
+            k_project<RPT, 4, 4, true><<<grid, block, 0, s>>>(H.row_ptr, H.col, H.val, H.rval, V, ld, H.dim, j, y, st, rb);
         } else {
-            if (tl.g == 8) k_project<RPT, 8, 2, false><<<grid, block, 0, s>>>(H.row_ptr, H.col, H.val, V, ld, H.dim, j, y, st, rb);
-            else if (tl.u == 1) k_project<RPT, 4, 1, false><<<grid, block, 0, s>>>(H.row_ptr, H.col, H.val, V, ld, H.dim, j, y, st, rb);
-            else k_project<RPT, 4, 4, false><<<grid, block, 0, s>>>(H.row_ptr, H.col, H.val, V, ld, H.dim, j, y, st, rb);
+            if (tl.g == 8) k_project<RPT, 8, 2, false><<<grid, block, 0, s>>>(H.row_ptr, H.col, H.val, H.rval, V, ld, H.dim, j, y, st, rb);
+            else if (tl.u == 1) k_project<RPT, 4, 1, false><<<grid, block, 0, s>>>(H.row_ptr, H.col, H.val, H.rval, V, ld, H.dim, j, y, st, rb);
+            else k_project<RPT, 4, 4, false><<<grid, block, 0, s>>>(H.row_ptr, H.col, H.val, H.rval, V, ld, H.dim, j, y, st, rb);
         }
     });
 }
@@ -1025,7 +1060,8 @@ hipError_t launch_scale_columns(const double2* src, double2* dst, int64_t ld, in
 
 hipError_t launch_spmv_only(const Tiling& tl, const Csr& H, const double2* x, double2* y, DevState* st,
                             const RedBuf& rb, hipStream_t s) {
-    k_spmv<4><<<tl.n_tiles_p, kBlock, 0, s>>>(H.row_ptr, H.col, H.val, x, y, H.dim, rb, kBlock * tl.rpt_p);
+    if (H.rval) k_spmv<4, double><<<tl.n_tiles_p, kBlock, 0, s>>>(H.row_ptr, H.col, H.rval, x, y, H.dim, rb, kBlock * tl.rpt_p);
+    else k_spmv<4, double2><<<tl.n_tiles_p, kBlock, 0, s>>>(H.row_ptr, H.col, H.val, x, y, H.dim, rb, kBlock * tl.rpt_p);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_sum_part<<<1, kBlock, 0, s>>>(st, rb);
@@ -1035,6 +1071,12 @@ hipError_t launch_spmv_only(const Tiling& tl, const Csr& H, const double2* x, do
 hipError_t launch_validate(const Csr& H, int check_hermitian, int* err, double* rowsum, hipStream_t s) {
     const int blocks = (H.dim + kBlock - 1) / kBlock;
     k_validate<<<blocks, kBlock, 0, s>>>(H.row_ptr, H.col, H.val, H.dim, H.nnz, check_hermitian, err, rowsum);
+    return hipGetLastError();
+}
+
+hipError_t launch_real_part(const double2* val, double* rval, int64_t n, hipStream_t s) {
+    const int blocks = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, 8192);
+    k_real_part<<<blocks, kBlock, 0, s>>>(val, rval, n);
     return hipGetLastError();
 }
 

@@ -86,7 +86,8 @@ struct RedBuf {
 struct JobView {
     const int* rp;
     const int* ci;
-    const double2* val;
+    const double2* val;  // complex entries, or
+    const double* rval;  // real entries (exactly one is set)
     double2* V;          // basis columns, leading dimension ld
     double2* y;          // raw product H V[:, j]
     DevState* st;
@@ -105,7 +106,8 @@ constexpr int kMaxGroup = 8;  // vectors sharing one sparse-matrix stream
 struct GroupView {
     const int* rp;
     const int* ci;
-    const double2* val;
+    const double2* val;    // complex entries, or
+    const double* rval;    // real entries (exactly one is set)
     int dim;
     int nv;                // jobs in the group (1..kMaxGroup)
     int job[kMaxGroup];    // indices into the round's JobView array
@@ -196,13 +198,18 @@ __device__ __forceinline__ double block_sum(double v, double* lds /* kWaves */) 
 // ----------------------------------------------------------------------- launchers
 struct Workspace;  // defined in api.hip
 
+// Exactly one of val (complex entries) and rval (real entries) is set.
 struct Csr {
     const int* row_ptr;
     const int* col;
     const double2* val;
+    const double* rval;
     int dim;
     int64_t nnz;
 };
+
+// bytes streamed per stored entry by a sparse product: value + column index
+inline double csr_entry_bytes(const Csr& c) { return c.rval ? 12.0 : 20.0; }
 
 // Row tiling of the row-parallel kernels.  The projection kernel's shape is chosen per matrix
 // by the autotuner: g lanes share a row of the sparse product, each keeping u nonzeros in
@@ -238,6 +245,7 @@ hipError_t launch_scale_columns(const double2* src, double2* dst, int64_t ld, in
                                 hipStream_t s);
 hipError_t launch_validate(const Csr& H, int check_hermitian, int* err, double* rowsum, hipStream_t s);
 hipError_t launch_norm1(const double* rowsum, int dim, double* out, hipStream_t s);
+hipError_t launch_real_part(const double2* val, double* rval, int64_t n, hipStream_t s);
 
 // batched launchers: items are (group or job, tile) pairs, one workgroup each
 hipError_t launch_gproject(int g, int u, int rpt, int nv_class, const JobView* jobs, const GroupView* groups,
@@ -283,6 +291,7 @@ struct te_hamiltonian_s {
     int* row_ptr = nullptr;
     int* col = nullptr;
     double2* val = nullptr;
+    double* rval = nullptr;
     double norm1 = 0.0;
     std::mutex mu;
     te::Workspace* ws = nullptr;

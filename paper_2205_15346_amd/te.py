@@ -28,6 +28,7 @@ TE_WARN_NUMERICAL = 1
 TE_WARN_QUADRATURE = 2
 TE_PTR_DEVICE = 1
 TE_CHECK_HERMITIAN = 2
+TE_STORE_COMPLEX = 4
 TE_MAX_KRYLOV = 64
 
 
@@ -142,6 +143,7 @@ _SIGS = {
     "te_hamiltonian_create": (_I, [ctypes.POINTER(_P), _I64, _I64, _P, _P, _P, ctypes.c_uint32, _P]),
     "te_hamiltonian_destroy": (_I, [_P]),
     "te_hamiltonian_info": (_I, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), _PD]),
+    "te_hamiltonian_real_values": (_I, [_P, _PI]),
     "te_workspace_bytes": (ctypes.c_size_t, [_I64, _I]),
     "te_set_allocator": (_I, [_P, _P, _P]),
     "te_evolve": (_I, [_P, _P, _P, _D, _D, _I, ctypes.POINTER(te_options), ctypes.POINTER(te_result), _P]),
@@ -230,6 +232,9 @@ class Hamiltonian:
         dim, nnz, n1 = _I64(), _I64(), _D()
         _check(_lib.te_hamiltonian_info(self._h, ctypes.byref(dim), ctypes.byref(nnz), ctypes.byref(n1)))
         self.dim, self.nnz, self.norm1 = dim.value, nnz.value, n1.value
+        rv = _I()
+        _check(_lib.te_hamiltonian_real_values(self._h, ctypes.byref(rv)))
+        self.real_values = bool(rv.value)  # entries stored as real (8 B) rather than complex
 
     @property
     def handle(self):
@@ -255,10 +260,13 @@ class Hamiltonian:
         self.destroy()
 
 
-def te_hamiltonian_create(row_ptr, col_idx, values, check_hermitian=False, stream=None) -> Hamiltonian:
-    """From host NumPy arrays (int32, int32, complex128) or CUDA tensors of the same dtypes."""
+def te_hamiltonian_create(row_ptr, col_idx, values, check_hermitian=False, stream=None,
+                          store_complex=False) -> Hamiltonian:
+    """From host NumPy arrays (int32, int32, complex128) or CUDA tensors of the same dtypes.
+    A matrix whose imaginary parts are all zero is stored with real entries unless
+    store_complex is set."""
     import torch
-    flags = TE_CHECK_HERMITIAN if check_hermitian else 0
+    flags = (TE_CHECK_HERMITIAN if check_hermitian else 0) | (TE_STORE_COMPLEX if store_complex else 0)
     keep = []
     if isinstance(values, torch.Tensor):
         flags |= TE_PTR_DEVICE
