@@ -664,7 +664,9 @@ te_status evolve_impl(te_hamiltonian h, const te_c128* v0, te_c128* v_out, doubl
         for (auto& v : w->pev) {
             while (v.size() < profile_events(mm)) {
                 hipEvent_t e;
-                TE_HIP(hipEventCreate(&e));
+                // timing only: no system-scope fence (no cache writeback per record); the
+                // restart's own event, recorded after these, is what the host waits on
+                TE_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
                 v.push_back(e);
             }
         }

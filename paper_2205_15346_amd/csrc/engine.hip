@@ -662,7 +662,7 @@ bool schedule_once(te_engine_s* e, std::unique_lock<std::mutex>& lk) {
         if (profiling(e)) {
             while ((int)e->pev.size() < 3 * p.m + 3) {
                 hipEvent_t ev;
-                r = hipEventCreate(&ev);
+                r = hipEventCreateWithFlags(&ev, hipEventDisableSystemFence);  // timing only
                 if (r != hipSuccess) break;
                 e->pev.push_back(ev);
             }
