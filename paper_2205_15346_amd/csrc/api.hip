@@ -199,20 +199,19 @@ hipError_t enqueue_restart(te_hamiltonian h, Workspace* w, hipStream_t s) {
 // restart with an event before the first and after every kernel (profiling mode)
 // restart with an event before the first and after every kernel (profiling mode);
 // iteration j: E[3j] project E[3j+1] fold E[3j+2] update E[3j+3]; then step, combine
+// Events are bound to the dispatches (E[0]: start of the first projection; E[3j+1], E[3j+2],
+// E[3j+3]: ends of projection, fold and update j; E[3m+1], E[3m+2]: ends of step and
+// recombination), so timing adds no packets between the kernels.
 hipError_t enqueue_restart_profiled(te_hamiltonian h, Workspace* w, hipStream_t s, std::vector<hipEvent_t>& E) {
-    hipError_t e = hipEventRecord(E[0], s);
+    hipError_t e = hipSuccess;
     for (int j = 0; j < w->m && e == hipSuccess; ++j) {
-        e = launch_project(w->tl, h->csr, w->V, w->ld, j, w->y, w->st, w->rb, s);
-        if (e == hipSuccess) e = hipEventRecord(E[3 * j + 1], s);
-        if (e == hipSuccess) e = launch_fold(j, w->st, w->rb, s);
-        if (e == hipSuccess) e = hipEventRecord(E[3 * j + 2], s);
-        if (e == hipSuccess) e = launch_update(w->tl, w->V, w->ld, w->dim, j, w->y, w->st, w->rb, s);
-        if (e == hipSuccess) e = hipEventRecord(E[3 * j + 3], s);
+        e = launch_project(w->tl, h->csr, w->V, w->ld, j, w->y, w->st, w->rb, s, j == 0 ? E[0] : nullptr,
+                           E[3 * j + 1]);
+        if (e == hipSuccess) e = launch_fold(j, w->st, w->rb, s, E[3 * j + 2]);
+        if (e == hipSuccess) e = launch_update(w->tl, w->V, w->ld, w->dim, j, w->y, w->st, w->rb, s, E[3 * j + 3]);
     }
-    if (e == hipSuccess) e = launch_step(w->st, w->rb, w->host_flag_dev, s);
-    if (e == hipSuccess) e = hipEventRecord(E[3 * w->m + 1], s);
-    if (e == hipSuccess) e = launch_combine(w->tl, w->V, w->ld, w->dim, w->st, s);
-    if (e == hipSuccess) e = hipEventRecord(E[3 * w->m + 2], s);
+    if (e == hipSuccess) e = launch_step(w->st, w->rb, w->host_flag_dev, s, E[3 * w->m + 1]);
+    if (e == hipSuccess) e = launch_combine(w->tl, w->V, w->ld, w->dim, w->st, s, E[3 * w->m + 2]);
     return e;
 }
 

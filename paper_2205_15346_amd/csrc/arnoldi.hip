@@ -20,6 +20,8 @@
 #include <algorithm>
 #include <type_traits>
 
+#include <hip/hip_ext.h>
+
 #include "te_internal.h"
 
 namespace te {
@@ -919,6 +921,15 @@ static hipError_t by_rpt_p(int rpt, F&& f) {
     return hipGetLastError();
 }
 
+// Launch with optional timing events bound to the dispatch (hipExtLaunchKernelGGL records the
+// kernel's own start/end, no marker packet of its own in the queue).
+template <typename... KArgs, typename... Args>
+static void launch_timed(void (*kernel)(KArgs...), dim3 grid, hipStream_t s, hipEvent_t start, hipEvent_t done,
+                         Args... args) {
+    if (start || done) hipExtLaunchKernelGGL(kernel, grid, dim3(kBlock), 0, s, start, done, 0, args...);
+    else hipLaunchKernelGGL(kernel, grid, dim3(kBlock), 0, s, args...);
+}
+
 static int grid_for(int dim) { return (int)std::min<int64_t>(((int64_t)dim + kBlock - 1) / kBlock, 4096); }
 
 // ----------------------------------------------------------------- batched launchers
@@ -1005,33 +1016,33 @@ hipError_t launch_copy(const double2* src, double2* dst, int dim, hipStream_t s)
 }
 
 hipError_t launch_project(const Tiling& tl, const Csr& H, const double2* V, int64_t ld, int j, double2* y,
-                          const DevState* st, const RedBuf& rb, hipStream_t s) {
+                          const DevState* st, const RedBuf& rb, hipStream_t s, hipEvent_t start, hipEvent_t done) {
     return by_rpt_p(tl.rpt_p, [&](auto r) {
         constexpr int RPT = decltype(r)::value;
-        const dim3 grid(tl.n_tiles_p), block(kBlock);
+        const dim3 grid(tl.n_tiles_p);
         if (tl.split) {  // the sparse product keeps one row per thread; rpt_p shapes the projections
             const dim3 g1((H.dim + kBlock - 1) / kBlock);
-            if (tl.g == 8) k_yspmv<1, 8, 2><<<g1, block, 0, s>>>(H.row_ptr, H.col, H.val, H.rval, V, ld, H.dim, j, y, st);
-            else if (tl.u == 1) k_yspmv<1, 4, 1><<<g1, block, 0, s>>>(H.row_ptr, H.col, H.val, H.rval, V, ld, H.dim, j, y, st);
-            else k_yspmv<1, 4, 4><<<g1, block, 0, s>>>(H.row_ptr, H.col, H.val, H.rval, V, ld, H.dim, j, y, st);
-            k_project<RPT, 4, 4, true><<<grid, block, 0, s>>>(H.row_ptr, H.col, H.val, H.rval, V, ld, H.dim, j, y, st, rb);
+            if (tl.g == 8) launch_timed(k_yspmv<1, 8, 2>, g1, s, start, nullptr, H.row_ptr, H.col, H.val, H.rval, V, ld, H.dim, j, y, st);
+            else if (tl.u == 1) launch_timed(k_yspmv<1, 4, 1>, g1, s, start, nullptr, H.row_ptr, H.col, H.val, H.rval, V, ld, H.dim, j, y, st);
+            else launch_timed(k_yspmv<1, 4, 4>, g1, s, start, nullptr, H.row_ptr, H.col, H.val, H.rval, V, ld, H.dim, j, y, st);
+            launch_timed(k_project<RPT, 4, 4, true>, grid, s, nullptr, done, H.row_ptr, H.col, H.val, H.rval, V, ld, H.dim, j, y, st, rb);
         } else {
-            if (tl.g == 8) k_project<RPT, 8, 2, false><<<grid, block, 0, s>>>(H.row_ptr, H.col, H.val, H.rval, V, ld, H.dim, j, y, st, rb);
-            else if (tl.u == 1) k_project<RPT, 4, 1, false><<<grid, block, 0, s>>>(H.row_ptr, H.col, H.val, H.rval, V, ld, H.dim, j, y, st, rb);
-            else k_project<RPT, 4, 4, false><<<grid, block, 0, s>>>(H.row_ptr, H.col, H.val, H.rval, V, ld, H.dim, j, y, st, rb);
+            if (tl.g == 8) launch_timed(k_project<RPT, 8, 2, false>, grid, s, start, done, H.row_ptr, H.col, H.val, H.rval, V, ld, H.dim, j, y, st, rb);
+            else if (tl.u == 1) launch_timed(k_project<RPT, 4, 1, false>, grid, s, start, done, H.row_ptr, H.col, H.val, H.rval, V, ld, H.dim, j, y, st, rb);
+            else launch_timed(k_project<RPT, 4, 4, false>, grid, s, start, done, H.row_ptr, H.col, H.val, H.rval, V, ld, H.dim, j, y, st, rb);
         }
     });
 }
 
-hipError_t launch_fold(int j, const DevState* st, const RedBuf& rb, hipStream_t s) {
-    k_fold<<<2 * (j + 1), kBlock, 0, s>>>(st, rb, j);
+hipError_t launch_fold(int j, const DevState* st, const RedBuf& rb, hipStream_t s, hipEvent_t done) {
+    launch_timed(k_fold, dim3(2 * (j + 1)), s, nullptr, done, st, rb, j);
     return hipGetLastError();
 }
 
 hipError_t launch_update(const Tiling& tl, double2* V, int64_t ld, int dim, int j, const double2* y,
-                         DevState* st, const RedBuf& rb, hipStream_t s) {
+                         DevState* st, const RedBuf& rb, hipStream_t s, hipEvent_t done) {
     return by_rpt(tl.rpt_u, [&](auto r) {
-        k_update<decltype(r)::value><<<tl.n_tiles_u, kBlock, 0, s>>>(V, ld, dim, j, y, st, rb);
+        launch_timed(k_update<decltype(r)::value>, dim3(tl.n_tiles_u), s, nullptr, done, V, ld, dim, j, y, st, rb);
     });
 }
 
@@ -1040,9 +1051,10 @@ hipError_t launch_last_norm(DevState* st, const RedBuf& rb, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_combine(const Tiling& tl, double2* V, int64_t ld, int dim, const DevState* st, hipStream_t s) {
+hipError_t launch_combine(const Tiling& tl, double2* V, int64_t ld, int dim, const DevState* st, hipStream_t s,
+                          hipEvent_t done) {
     return by_rpt(tl.rpt_u, [&](auto r) {
-        k_combine<decltype(r)::value><<<tl.n_tiles_u, kBlock, 0, s>>>(V, ld, dim, st);
+        launch_timed(k_combine<decltype(r)::value>, dim3(tl.n_tiles_u), s, nullptr, done, V, ld, dim, st);
     });
 }
 

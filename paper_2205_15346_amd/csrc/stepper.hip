@@ -11,6 +11,8 @@
 //      substeps, end snap);
 //   5. omega = exp(-iJ tau) e_1 scaled to the raw basis columns, and the restart controller:
 //      time, accumulated bound, roundoff estimate (eq. numericalError), warnings, done flag.
+#include <hip/hip_ext.h>
+
 #include "te_internal.h"
 
 namespace te {
@@ -659,8 +661,9 @@ __global__ __launch_bounds__(kBlock) void k_integral_only(int k, const double* l
 
 }  // namespace
 
-hipError_t launch_step(DevState* st, const RedBuf& rb, int* host_flag, hipStream_t s) {
-    hipLaunchKernelGGL(k_step, dim3(1), dim3(kBlock), 0, s, st, rb, host_flag);
+hipError_t launch_step(DevState* st, const RedBuf& rb, int* host_flag, hipStream_t s, hipEvent_t done) {
+    if (done) hipExtLaunchKernelGGL(k_step, dim3(1), dim3(kBlock), 0, s, nullptr, done, 0, st, rb, host_flag);
+    else hipLaunchKernelGGL(k_step, dim3(1), dim3(kBlock), 0, s, st, rb, host_flag);
     return hipGetLastError();
 }
 

@@ -230,15 +230,19 @@ int max_tiles(int dim);  // tiles of the finest tiling (rpt = 1): sizes the part
 
 hipError_t launch_setup(DevState* st, const Problem& prob, hipStream_t s);
 hipError_t launch_copy(const double2* src, double2* dst, int dim, hipStream_t s);
+// The optional events of the single-solve launchers are bound to the dispatches themselves
+// (profiling: `start` at the first kernel's start, `done` at the last kernel's end).
 hipError_t launch_project(const Tiling& tl, const Csr& H, const double2* V, int64_t ld, int j, double2* y,
-                          const DevState* st, const RedBuf& rb, hipStream_t s);
-hipError_t launch_fold(int j, const DevState* st, const RedBuf& rb, hipStream_t s);
+                          const DevState* st, const RedBuf& rb, hipStream_t s, hipEvent_t start = nullptr,
+                          hipEvent_t done = nullptr);
+hipError_t launch_fold(int j, const DevState* st, const RedBuf& rb, hipStream_t s, hipEvent_t done = nullptr);
 hipError_t launch_update(const Tiling& tl, double2* V, int64_t ld, int dim, int j, const double2* y,
-                         DevState* st, const RedBuf& rb, hipStream_t s);
+                         DevState* st, const RedBuf& rb, hipStream_t s, hipEvent_t done = nullptr);
 hipError_t launch_last_norm(DevState* st, const RedBuf& rb, hipStream_t s);
-hipError_t launch_combine(const Tiling& tl, double2* V, int64_t ld, int dim, const DevState* st, hipStream_t s);
+hipError_t launch_combine(const Tiling& tl, double2* V, int64_t ld, int dim, const DevState* st, hipStream_t s,
+                          hipEvent_t done = nullptr);
 hipError_t launch_output(const double2* V, double2* out, int dim, const DevState* st, hipStream_t s);
-hipError_t launch_step(DevState* st, const RedBuf& rb, int* host_flag, hipStream_t s);
+hipError_t launch_step(DevState* st, const RedBuf& rb, int* host_flag, hipStream_t s, hipEvent_t done = nullptr);
 hipError_t launch_spmv_only(const Tiling& tl, const Csr& H, const double2* x, double2* y, DevState* st,
                             const RedBuf& rb, hipStream_t s);
 hipError_t launch_scale_columns(const double2* src, double2* dst, int64_t ld, int dim, int k, const DevState* st,
