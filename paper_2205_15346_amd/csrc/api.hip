@@ -64,6 +64,8 @@ void dev_free(void* p) {
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+size_t basis_ld(int64_t dim) { return align_up((size_t)dim, 64); }
+
 }  // namespace te
 
 // ------------------------------------------------------------------------- workspace
@@ -89,7 +91,7 @@ struct Workspace {
 
     static size_t layout(int dim, int m, const Tiling& tl, size_t* off_y, size_t* off_part, size_t* off_npart,
                          size_t* off_red, size_t* off_st) {
-        const size_t ld = align_up((size_t)dim, 64);
+        const size_t ld = basis_ld(dim);
         size_t o = 0;
         o += (size_t)m * ld * sizeof(double2);
         *off_y = o;
@@ -146,7 +148,7 @@ te_status make_workspace(te_hamiltonian h, int m, Workspace** out) {
     if (!w) return fail(TE_ERR_OUT_OF_MEMORY, "host allocation failed");
     w->dim = h->csr.dim;
     w->m = m;
-    w->ld = (int64_t)align_up((size_t)w->dim, 64);
+    w->ld = (int64_t)basis_ld(w->dim);
     w->tl = handle_tiling(h);
     size_t oy, op, on, orr, os;
     w->bytes = Workspace::layout(w->dim, m, w->tl, &oy, &op, &on, &orr, &os);

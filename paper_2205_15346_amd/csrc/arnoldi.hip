@@ -260,10 +260,14 @@ __device__ __forceinline__ void project_body(const int* __restrict__ rp, const i
         tile_spmv<G, U>(rp, ci, val, rval, x, r0, r1, y, ytile);
         __syncthreads();
     }
+    // Rows past the end of a ragged tile read row r1 - 1 and are weighted by zero, so the loads
+    // of a batch carry no branches and are all issued before the first one is used.
     double2 yq[RPT], xq[RPT];
+    int rr[RPT];
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
         const int r = r0 + tid + q * kBlock;
+        rr[q] = min(r, r1 - 1);
         if (r < r1) {
             yq[q] = FROM_Y ? y[r] : ytile[r - r0];
             xq[q] = x[r];
@@ -274,7 +278,8 @@ __device__ __forceinline__ void project_body(const int* __restrict__ rp, const i
     }
     // projections on columns i_lo..j (i_lo = j - 1 in three-term mode) in batches of CB: with
     // four rows per thread, batches of 4 keep the loads of a batch in flight without spilling
-    // the occupancy below four waves per SIMD
+    // the occupancy below four waves per SIMD.  Columns past j in the last batch re-read
+    // column j (cached); their sums are not stored.
     constexpr int CB = RPT >= 4 ? 4 : 8;
     const int i_lo = (st->p.three_term && j >= 1) ? j - 1 : 0;
     for (int i0 = i_lo; i0 <= j; i0 += CB) {
@@ -282,18 +287,12 @@ __device__ __forceinline__ void project_body(const int* __restrict__ rp, const i
 #pragma unroll
         for (int b = 0; b < CB; ++b) {
             double2 cy = make_double2(0.0, 0.0), cx = make_double2(0.0, 0.0);
-            const int i = i0 + b;
-            if (i <= j) {
-                const double2* __restrict__ vi = V + (int64_t)i * ld;
+            const double2* __restrict__ vi = V + (int64_t)min(i0 + b, j) * ld;
 #pragma unroll
-                for (int q = 0; q < RPT; ++q) {
-                    const int r = r0 + tid + q * kBlock;
-                    if (r < r1) {
-                        const double2 v = load_stream(vi + r);
-                        cy = cfma_conj(v, yq[q], cy);
-                        cx = cfma_conj(v, xq[q], cx);
-                    }
-                }
+            for (int q = 0; q < RPT; ++q) {
+                const double2 v = load_stream(vi + rr[q]);
+                cy = cfma_conj(v, yq[q], cy);
+                cx = cfma_conj(v, xq[q], cx);
             }
             a[4 * b] = cy.x;
             a[4 * b + 1] = cy.y;

@@ -53,7 +53,7 @@ struct JobLayout {
 
 JobLayout job_layout(int dim, int m) {
     JobLayout L{};
-    const uint64_t ld = align_up((size_t)dim, 64);
+    const uint64_t ld = basis_ld(dim);
     const uint64_t tiles = (uint64_t)ceil_div(dim, kTileRows);
     uint64_t o = 0;
     L.v = o;
@@ -206,7 +206,7 @@ JobView job_view(te_engine_s* e, const JobRec& j, int rpt_u) {
     v.rb.n_norm = (int)ceil_div(j.dim, (int64_t)kBlock * rpt_u);
     v.v0 = j.v0;
     v.out = j.out;
-    v.ld = (int64_t)align_up((size_t)j.dim, 64);
+    v.ld = (int64_t)basis_ld(j.dim);
     v.id = j.id;
     v.dim = j.dim;
     v.slot = j.slot;

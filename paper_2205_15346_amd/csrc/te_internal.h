@@ -286,6 +286,8 @@ void* dev_alloc(size_t bytes);                             // te_set_allocator h
 void dev_free(void* p);
 te_status check_options(const te_options& o);
 size_t align_up(size_t x, size_t a);
+// leading dimension (elements) of a basis: one column per Krylov vector
+size_t basis_ld(int64_t dim);
 
 }  // namespace te
 
