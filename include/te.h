@@ -95,8 +95,10 @@ typedef struct {
 } te_result;
 
 /* te_options.flags bit: time every kernel of te_evolve with HIP events on the caller's
- * stream (restarts are then launched directly instead of as a graph) and record the
- * per-kernel durations and algorithmic bytes, read back with te_last_profile(). */
+ * stream (restarts are then launched directly instead of as a graph; the events are bound to
+ * the kernel dispatches, so the timed solve runs at the graph's speed) and record the
+ * per-kernel durations and algorithmic bytes, read back with te_last_profile().  A class's
+ * duration runs from the end of the kernel before it to its own end. */
 #define TE_OPT_PROFILE 1u
 
 /* te_options.flags bit: build each Krylov basis with the three-term recurrence exactly as
