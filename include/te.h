@@ -154,6 +154,49 @@ te_status te_hamiltonian_create(te_hamiltonian* out, int64_t dim, int64_t nnz,
 
 /* *real_values = 1 when the handle stores real entries (see te_hamiltonian_create), else 0. */
 te_status te_hamiltonian_real_values(te_hamiltonian h, int32_t* real_values);
+
+/* Copies the handle's CSR out: row_ptr[dim+1], col_idx[nnz], values[nnz] (complex; real
+ * entries are returned with zero imaginary parts).  Device pointers with TE_PTR_DEVICE, else
+ * host.  Any of the three may be NULL (not copied).  Synchronous. */
+te_status te_hamiltonian_copy_csr(te_hamiltonian h, int32_t* row_ptr, int32_t* col_idx, te_c128* values,
+                                  uint32_t flags, void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * The paper's exemplary Hamiltonian built on the device (Sec. "Exemplary System", eq.
+ * fullHamiltonianSimple with the conserved totals of eq. subsetOccupations): modes a_0, b_0
+ * with N_0 = n_0 + m_0 bosons and K + K' memory qubits a_1..a_K, a'_1..a'_K' with N_m
+ * excitations,
+ *   H = C_0 (a_0^+ b_0 + h.c.) + eps_m (1 - n_0/N_c) sum_k n_k + eps_m (1 - n_0/(N_c - dN_c)) sum_k' n'_k'
+ *     + C_m [ sum_{k,k'} f_1(k,k') (a_k^+ a'_k' + h.c.) + sum_{k<l} f_2(k,l) (a_k^+ a_l + h.c.)
+ *             + sum_{k'<l'} f_3(k',l') (a'_k'^+ a'_l' + h.c.) ],
+ * f_i = F_i - 1 if F_i < 1/2 else F_i, F_i(k,l) = (sqrt(2) (k + dk_i)^3 + sqrt(7) (l + dl_i)^5) mod 1,
+ * dk_1 = dk_2 = 1, dk_3 = K + 1, dl_1 = dl_3 = K + 1, dl_2 = 1 (the f_i are evaluated on the
+ * host; every matrix entry on the device).  Basis: row = (N_0 - n_0) binom(K+K', N_m) + rank
+ * of the qubit configuration, both sectors in descending lexicographic order of the occupation
+ * tuples (modes ordered a_1..a_K, a'_1..a'_K').  The matrix is real: the handle stores 8-byte
+ * entries.  Matrix creation is the memory limit of the paper's CPU program (Sec. "Analysis of
+ * Performance"); here no basis, lookup table or triplet list exists on the host. */
+typedef struct {
+    int32_t K, Kp;  /* memory qubits a_k and a'_k' (K >= 1, K + K' <= 63) */
+    int32_t N0;     /* bosons in a_0, b_0 (>= 0) */
+    int32_t Nm;     /* memory excitations, 0 <= N_m <= K */
+    double eps_m;   /* memory-mode energy */
+    double Nc;      /* critical occupation N_c */
+    double dNc;     /* 0 < dN_c < N_c */
+    double C0, Cm;  /* couplings */
+} te_memory_burden;
+
+/* The paper's parameters of its Fig. 1 system: K = K' = 4, N_0 = 20, N_m = 2, eps_m = sqrt(20),
+ * N_c = 20, dN_c = 12, C_0 = C_m = 1. */
+void te_memory_burden_defaults(te_memory_burden* p);
+
+/* Builds the matrix in device memory and returns its handle; *initial_index (may be NULL)
+ * receives the basis index of the initial state of eq. initialStateSimple
+ * (n_0 = N_0, a_1..a_{N_m} occupied).  TE_ERR_INVALID_ARG for parameters out of range,
+ * TE_ERR_UNSUPPORTED when dim or nnz does not fit int32 or a row exceeds 512 entries.
+ * Synchronous. */
+te_status te_hamiltonian_create_memory_burden(te_hamiltonian* out, const te_memory_burden* p,
+                                              int64_t* initial_index, void* stream);
 te_status te_hamiltonian_destroy(te_hamiltonian h); /* frees everything the handle owns */
 te_status te_hamiltonian_info(te_hamiltonian h, int64_t* dim, int64_t* nnz, double* norm1);
 

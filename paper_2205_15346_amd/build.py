@@ -12,7 +12,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libtimeevolve.so")
-SOURCES = ["arnoldi.hip", "stepper.hip", "sampling.hip", "api.hip", "engine.hip"]
+SOURCES = ["arnoldi.hip", "stepper.hip", "sampling.hip", "api.hip", "engine.hip", "models.hip"]
 ARCH = os.environ.get("TE_OFFLOAD_ARCH", "gfx950")
 
 

@@ -498,6 +498,27 @@ size_t te_workspace_bytes(int64_t dim, int32_t m) {
     return Workspace::layout((int)dim, mm, default_tiling((int)dim), &a, &b, &c, &d, &e);
 }
 
+// Validates a handle's CSR on the device (structure, column range, finite entries, optionally
+// Hermitian with sorted columns) and stores its 1-norm.  err (>= 4 bytes) and rowsum (dim + 8
+// doubles) are device scratch; *herr receives the error bits (32: an imaginary part is nonzero).
+static te_status validate_handle(te_hamiltonian h, int check_hermitian, int* err, double* rowsum, int* herr,
+                                 hipStream_t s) {
+    const int dim = h->csr.dim;
+    double norm1 = 0.0;
+    TE_HIP(hipMemsetAsync(err, 0, sizeof(int), s));
+    TE_HIP(launch_validate(h->csr, check_hermitian, err, rowsum, s));
+    TE_HIP(launch_norm1(rowsum, dim, rowsum + dim, s));
+    TE_HIP(hipMemcpyAsync(herr, err, sizeof(int), hipMemcpyDeviceToHost, s));
+    TE_HIP(hipMemcpyAsync(&norm1, rowsum + dim, sizeof(double), hipMemcpyDeviceToHost, s));
+    TE_HIP(hipStreamSynchronize(s));
+    if (*herr & (1 | 2 | 4 | 8))
+        return fail(TE_ERR_INVALID_CSR, "invalid CSR (code " + std::to_string(*herr) + ": 1 structure, 2 column range, "
+                                        "4 non-finite value, 8 unsorted columns)");
+    if (*herr & 16) return fail(TE_ERR_NOT_HERMITIAN, "H differs from its conjugate transpose");
+    h->norm1 = norm1;
+    return TE_OK;
+}
+
 te_status te_hamiltonian_create(te_hamiltonian* out, int64_t dim, int64_t nnz, const int32_t* row_ptr,
                                 const int32_t* col_idx, const te_c128* values, uint32_t flags, void* stream) {
     if (!out || !row_ptr || !col_idx || !values) return fail(TE_ERR_INVALID_ARG, "null pointer");
@@ -522,7 +543,6 @@ te_status te_hamiltonian_create(te_hamiltonian* out, int64_t dim, int64_t nnz, c
     const hipMemcpyKind kind = (flags & TE_PTR_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     te_status rc = TE_OK;
     int herr = 0;
-    double norm1 = 0.0;
     auto chk = [&](hipError_t e, const char* what) {
         if (e != hipSuccess && rc == TE_OK)
             rc = fail(e == hipErrorOutOfMemory ? TE_ERR_OUT_OF_MEMORY : TE_ERR_DEVICE,
@@ -538,17 +558,9 @@ te_status te_hamiltonian_create(te_hamiltonian* out, int64_t dim, int64_t nnz, c
     h->csr.rval = nullptr;
     h->csr.dim = (int)dim;
     h->csr.nnz = nnz;
-    if (rc == TE_OK) chk(launch_validate(h->csr, (flags & TE_CHECK_HERMITIAN) ? 1 : 0, err, rowsum, s), "validate");
-    if (rc == TE_OK) chk(launch_norm1(rowsum, (int)dim, rowsum + dim, s), "norm1");
-    if (rc == TE_OK) chk(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s), "copy status");
-    if (rc == TE_OK) chk(hipMemcpyAsync(&norm1, rowsum + dim, sizeof(double), hipMemcpyDeviceToHost, s), "copy norm");
-    if (rc == TE_OK) chk(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (rc == TE_OK) rc = validate_handle(h, (flags & TE_CHECK_HERMITIAN) ? 1 : 0, err, rowsum, &herr, s);
     dev_free(rowsum);
     dev_free(err);
-    if (rc == TE_OK && (herr & (1 | 2 | 4 | 8)))
-        rc = fail(TE_ERR_INVALID_CSR, "invalid CSR (code " + std::to_string(herr) + ": 1 structure, 2 column range, "
-                                      "4 non-finite value, 8 unsorted columns)");
-    if (rc == TE_OK && (herr & 16)) rc = fail(TE_ERR_NOT_HERMITIAN, "H differs from its conjugate transpose");
     if (rc == TE_OK && !(herr & 32) && !(flags & TE_STORE_COMPLEX)) {
         // every imaginary part is zero: keep the real parts only
         h->rval = (double*)dev_alloc(nnz * sizeof(double));
@@ -566,7 +578,6 @@ te_status te_hamiltonian_create(te_hamiltonian* out, int64_t dim, int64_t nnz, c
         delete h;
         return rc;
     }
-    h->norm1 = norm1;
     *out = h;
     return TE_OK;
 }
@@ -581,6 +592,163 @@ te_status te_hamiltonian_destroy(te_hamiltonian h) {
 te_status te_hamiltonian_real_values(te_hamiltonian h, int32_t* real_values) {
     if (!h || !real_values) return fail(TE_ERR_INVALID_ARG, "null pointer");
     *real_values = h->csr.rval ? 1 : 0;
+    return TE_OK;
+}
+
+te_status te_hamiltonian_copy_csr(te_hamiltonian h, int32_t* row_ptr, int32_t* col_idx, te_c128* values,
+                                  uint32_t flags, void* stream) {
+    if (!h) return fail(TE_ERR_INVALID_ARG, "null handle");
+    if (flags & ~TE_PTR_DEVICE) return fail(TE_ERR_INVALID_ARG, "unknown flags");
+    hipStream_t s = (hipStream_t)stream;
+    const bool dev = (flags & TE_PTR_DEVICE) != 0;
+    const hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    const int64_t dim = h->csr.dim, nnz = h->csr.nnz;
+    if (row_ptr) TE_HIP(hipMemcpyAsync(row_ptr, h->csr.row_ptr, (dim + 1) * sizeof(int), kind, s));
+    if (col_idx) TE_HIP(hipMemcpyAsync(col_idx, h->csr.col, nnz * sizeof(int), kind, s));
+    if (values) {
+        if (h->csr.val) {
+            TE_HIP(hipMemcpyAsync(values, h->csr.val, nnz * sizeof(double2), kind, s));
+        } else if (dev) {
+            TE_HIP(launch_expand_real(h->csr.rval, (double2*)values, nnz, s));
+        } else {
+            std::vector<double> tmp;
+            try {
+                tmp.resize((size_t)nnz);
+            } catch (...) {
+                return fail(TE_ERR_OUT_OF_MEMORY, "host buffer for the real entries");
+            }
+            TE_HIP(hipMemcpyAsync(tmp.data(), h->csr.rval, nnz * sizeof(double), hipMemcpyDeviceToHost, s));
+            TE_HIP(hipStreamSynchronize(s));
+            for (int64_t k = 0; k < nnz; ++k) {
+                values[k].re = tmp[(size_t)k];
+                values[k].im = 0.0;
+            }
+        }
+    }
+    TE_HIP(hipStreamSynchronize(s));
+    return TE_OK;
+}
+
+void te_memory_burden_defaults(te_memory_burden* p) {
+    if (!p) return;
+    p->K = 4;
+    p->Kp = 4;
+    p->N0 = 20;
+    p->Nm = 2;
+    p->eps_m = std::sqrt(20.0);
+    p->Nc = 20.0;
+    p->dNc = 12.0;
+    p->C0 = 1.0;
+    p->Cm = 1.0;
+}
+
+te_status te_hamiltonian_create_memory_burden(te_hamiltonian* out, const te_memory_burden* p,
+                                              int64_t* initial_index, void* stream) {
+    if (!out || !p) return fail(TE_ERR_INVALID_ARG, "null pointer");
+    *out = nullptr;
+    const te_memory_burden P = *p;
+    const int n = P.K + P.Kp;
+    if (P.K < 1 || P.Kp < 0 || n > 63 || P.N0 < 0 || P.Nm < 0 || P.Nm > P.K)
+        return fail(TE_ERR_INVALID_ARG, "need K >= 1, K' >= 0, K + K' <= 63, N_0 >= 0, 0 <= N_m <= K");
+    if (!std::isfinite(P.eps_m) || !std::isfinite(P.Nc) || !std::isfinite(P.dNc) || !std::isfinite(P.C0) ||
+        !std::isfinite(P.Cm) || !(P.dNc > 0.0) || !(P.dNc < P.Nc))
+        return fail(TE_ERR_INVALID_ARG, "need finite parameters and 0 < dN_c < N_c");
+    // binomials (exact in int64 up to binom(63, 31) < 2^63)
+    std::vector<int64_t> binom(64 * 64, 0);
+    for (int a = 0; a < 64; ++a) {
+        binom[(size_t)a * 64] = 1;
+        for (int b = 1; b <= a; ++b)
+            binom[(size_t)a * 64 + b] = binom[(size_t)(a - 1) * 64 + b - 1] + (b <= a - 1 ? binom[(size_t)(a - 1) * 64 + b] : 0);
+    }
+    const int64_t C = binom[(size_t)n * 64 + P.Nm];
+    const int64_t Q = (int64_t)P.Nm * (n - P.Nm);
+    const int64_t max_len = 1 + Q + (P.N0 > 0 ? 2 : 0);
+    if (C > ((int64_t)1 << 31) / (P.N0 + 1)) return fail(TE_ERR_UNSUPPORTED, "dimension does not fit int32");
+    const int64_t dim = C * (P.N0 + 1);
+    const int64_t nnz = C * ((int64_t)(P.N0 + 1) * (1 + Q) + 2 * (int64_t)P.N0);
+    if (dim >= ((int64_t)1 << 31) - 1 || nnz >= ((int64_t)1 << 31)) return fail(TE_ERR_UNSUPPORTED, "nnz does not fit int32");
+    int slots = 1;
+    while (slots < max_len) slots <<= 1;
+    if (slots > 512) return fail(TE_ERR_UNSUPPORTED, "a row would exceed 512 entries");
+    // hopping amplitudes C_m f_i of the qubit pairs, on the host as the paper writes them
+    auto f = [&](int i, int k, int l) {
+#pragma clang fp contract(off)
+        const int dk = (i == 3) ? P.K + 1 : 1;
+        const int dl = (i == 2) ? 1 : P.K + 1;
+        const double x = (double)(k + dk), y = (double)(l + dl);
+        const double a = std::sqrt(2.0) * (x * x * x);
+        const double b = std::sqrt(7.0) * (y * y * y * y * y);
+        const double F = std::fmod(a + b, 1.0);
+        return F < 0.5 ? F - 1.0 : F;
+    };
+    std::vector<double> hop(64 * 64, 0.0);
+    auto set_pair = [&](int u, int v, double amp) {
+        hop[(size_t)u * 64 + v] = amp;
+        hop[(size_t)v * 64 + u] = amp;
+    };
+    for (int k = 1; k <= P.K; ++k)
+        for (int kp = 1; kp <= P.Kp; ++kp) set_pair(k - 1, P.K + kp - 1, P.Cm * f(1, k, kp));
+    for (int k = 1; k <= P.K; ++k)
+        for (int l = k + 1; l <= P.K; ++l) set_pair(k - 1, l - 1, P.Cm * f(2, k, l));
+    for (int kp = 1; kp <= P.Kp; ++kp)
+        for (int lp = kp + 1; lp <= P.Kp; ++lp) set_pair(P.K + kp - 1, P.K + lp - 1, P.Cm * f(3, kp, lp));
+
+    hipStream_t s = (hipStream_t)stream;
+    auto* h = new (std::nothrow) te_hamiltonian_s();
+    if (!h) return fail(TE_ERR_OUT_OF_MEMORY, "host allocation failed");
+    h->row_ptr = (int*)dev_alloc((size_t)(dim + 1) * sizeof(int));
+    h->col = (int*)dev_alloc((size_t)nnz * sizeof(int));
+    h->rval = (double*)dev_alloc((size_t)nnz * sizeof(double));
+    int64_t* d_binom = (int64_t*)dev_alloc(binom.size() * sizeof(int64_t));
+    double* d_hop = (double*)dev_alloc(hop.size() * sizeof(double));
+    double* rowsum = (double*)dev_alloc((size_t)dim * sizeof(double) + 64);
+    int* err = (int*)dev_alloc(64);
+    auto cleanup = [&]() {
+        dev_free(d_binom);
+        dev_free(d_hop);
+        dev_free(rowsum);
+        dev_free(err);
+    };
+    if (!h->row_ptr || !h->col || !h->rval || !d_binom || !d_hop || !rowsum || !err) {
+        cleanup();
+        delete h;
+        return fail(TE_ERR_OUT_OF_MEMORY, "device allocation for the matrix failed");
+    }
+    h->csr.row_ptr = h->row_ptr;
+    h->csr.col = h->col;
+    h->csr.val = nullptr;
+    h->csr.rval = h->rval;
+    h->csr.dim = (int)dim;
+    h->csr.nnz = nnz;
+    MemoryBurdenDev M;
+    M.n = n;
+    M.K = P.K;
+    M.Nm = P.Nm;
+    M.N0 = P.N0;
+    M.C = C;
+    M.slots = slots;
+    M.dim = dim;
+    M.eps_m = P.eps_m;
+    M.Nc = P.Nc;
+    M.NcMinusDNc = P.Nc - P.dNc;
+    M.C0 = P.C0;
+    M.binom = d_binom;
+    M.hop = d_hop;
+    te_status rc = TE_OK;
+    hipError_t e = hipMemcpyAsync(d_binom, binom.data(), binom.size() * sizeof(int64_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_hop, hop.data(), hop.size() * sizeof(double), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_memory_burden(M, h->row_ptr, h->col, h->rval, s);
+    if (e != hipSuccess) rc = fail(TE_ERR_DEVICE, std::string("building the matrix: ") + hipGetErrorString(e));
+    int herr = 0;
+    // the construction is checked like any uploaded matrix (sorted, in range, Hermitian)
+    if (rc == TE_OK) rc = validate_handle(h, 1, err, rowsum, &herr, s);
+    cleanup();
+    if (rc != TE_OK) {
+        delete h;
+        return rc;
+    }
+    if (initial_index) *initial_index = 0;  // n_0 = N_0 (block 0) and the first configuration
+    *out = h;
     return TE_OK;
 }
 

@@ -829,8 +829,12 @@ __global__ __launch_bounds__(kBlock) void k_sum_part(DevState* st, RedBuf rb) {
 // ------------------------------------------------------------------ CSR validation
 // err bits: 1 structure, 2 column range, 4 non-finite, 8 unsorted (Hermitian check), 16 not Hermitian;
 // bit 32 (not an error) marks a nonzero imaginary part
+__device__ __forceinline__ double2 as_complex(double2 v) { return v; }
+__device__ __forceinline__ double2 as_complex(double v) { return make_double2(v, 0.0); }
+
+template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_validate(const int* __restrict__ rp, const int* __restrict__ ci,
-                                                      const double2* __restrict__ val, int dim, int64_t nnz,
+                                                      const VT* __restrict__ val, int dim, int64_t nnz,
                                                       int check_herm, int* err, double* rowsum) {
     const int r = blockIdx.x * kBlock + threadIdx.x;
     if (r >= dim) return;
@@ -846,7 +850,7 @@ __global__ __launch_bounds__(kBlock) void k_validate(const int* __restrict__ rp,
     double sum = 0.0;
     for (int k = kb; k < ke; ++k) {
         const int c = ci[k];
-        const double2 v = val[k];
+        const double2 v = as_complex(val[k]);
         if (c < 0 || c >= dim) {
             e |= 2;
             continue;
@@ -866,7 +870,7 @@ __global__ __launch_bounds__(kBlock) void k_validate(const int* __restrict__ rp,
                 const int cm = ci[mid];
                 if (cm == r) {
                     found = true;
-                    w = val[mid];
+                    w = as_complex(val[mid]);
                     break;
                 }
                 if (cm < r) lo = mid + 1;
@@ -880,6 +884,12 @@ __global__ __launch_bounds__(kBlock) void k_validate(const int* __restrict__ rp,
     }
     rowsum[r] = sum;
     if (e) atomicOr(err, e);
+}
+
+__global__ __launch_bounds__(kBlock) void k_expand_real(const double* __restrict__ rval, double2* __restrict__ val,
+                                                         int64_t n) {
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < n; k += (int64_t)gridDim.x * kBlock)
+        val[k] = make_double2(rval[k], 0.0);
 }
 
 __global__ __launch_bounds__(kBlock) void k_real_part(const double2* __restrict__ val, double* __restrict__ rval,
@@ -1081,13 +1091,20 @@ hipError_t launch_spmv_only(const Tiling& tl, const Csr& H, const double2* x, do
 
 hipError_t launch_validate(const Csr& H, int check_hermitian, int* err, double* rowsum, hipStream_t s) {
     const int blocks = (H.dim + kBlock - 1) / kBlock;
-    k_validate<<<blocks, kBlock, 0, s>>>(H.row_ptr, H.col, H.val, H.dim, H.nnz, check_hermitian, err, rowsum);
+    if (H.rval) k_validate<double><<<blocks, kBlock, 0, s>>>(H.row_ptr, H.col, H.rval, H.dim, H.nnz, check_hermitian, err, rowsum);
+    else k_validate<double2><<<blocks, kBlock, 0, s>>>(H.row_ptr, H.col, H.val, H.dim, H.nnz, check_hermitian, err, rowsum);
     return hipGetLastError();
 }
 
 hipError_t launch_real_part(const double2* val, double* rval, int64_t n, hipStream_t s) {
     const int blocks = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, 8192);
     k_real_part<<<blocks, kBlock, 0, s>>>(val, rval, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_expand_real(const double* rval, double2* val, int64_t n, hipStream_t s) {
+    const int blocks = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, 8192);
+    k_expand_real<<<blocks, kBlock, 0, s>>>(rval, val, n);
     return hipGetLastError();
 }
 

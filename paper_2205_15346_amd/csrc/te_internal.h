@@ -250,6 +250,20 @@ hipError_t launch_scale_columns(const double2* src, double2* dst, int64_t ld, in
 hipError_t launch_validate(const Csr& H, int check_hermitian, int* err, double* rowsum, hipStream_t s);
 hipError_t launch_norm1(const double* rowsum, int dim, double* out, hipStream_t s);
 hipError_t launch_real_part(const double2* val, double* rval, int64_t n, hipStream_t s);
+hipError_t launch_expand_real(const double* rval, double2* val, int64_t n, hipStream_t s);
+
+// Device construction of the paper's exemplary Hamiltonian (models.hip): sizes, parameters and
+// device tables prepared by te_hamiltonian_create_memory_burden.
+struct MemoryBurdenDev {
+    int n, K, Nm, N0;      // qubit modes (K + K'), a-type qubits, excitations, bosons
+    int64_t C;             // qubit configurations binom(n, Nm)
+    int slots;             // power of two >= longest row, <= 512
+    int64_t dim;
+    double eps_m, Nc, NcMinusDNc, C0;
+    const int64_t* binom;  // [64 * 64] binomials
+    const double* hop;     // [64 * 64] symmetric hopping amplitudes of the qubit pairs
+};
+hipError_t launch_memory_burden(const MemoryBurdenDev& M, int* row_ptr, int* col, double* val, hipStream_t s);
 
 // batched launchers: items are (group or job, tile) pairs, one workgroup each
 hipError_t launch_gproject(int g, int u, int rpt, int nv_class, const JobView* jobs, const GroupView* groups,

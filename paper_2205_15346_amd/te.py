@@ -57,6 +57,12 @@ TE_OPT_LANCZOS3 = 2
 KERNEL_CLASSES = ("project", "update", "step", "combine", "fold")
 
 
+class te_memory_burden(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_int32), ("Kp", ctypes.c_int32), ("N0", ctypes.c_int32), ("Nm", ctypes.c_int32),
+                ("eps_m", ctypes.c_double), ("Nc", ctypes.c_double), ("dNc", ctypes.c_double),
+                ("C0", ctypes.c_double), ("Cm", ctypes.c_double)]
+
+
 class te_profile(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64 * 5), ("seconds", ctypes.c_double * 5), ("bytes", ctypes.c_double * 5)]
 
@@ -144,6 +150,9 @@ _SIGS = {
     "te_hamiltonian_destroy": (_I, [_P]),
     "te_hamiltonian_info": (_I, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), _PD]),
     "te_hamiltonian_real_values": (_I, [_P, _PI]),
+    "te_hamiltonian_copy_csr": (_I, [_P, _P, _P, _P, ctypes.c_uint32, _P]),
+    "te_memory_burden_defaults": (None, [ctypes.c_void_p]),
+    "te_hamiltonian_create_memory_burden": (_I, [ctypes.POINTER(_P), ctypes.c_void_p, ctypes.POINTER(_I64), _P]),
     "te_workspace_bytes": (ctypes.c_size_t, [_I64, _I]),
     "te_set_allocator": (_I, [_P, _P, _P]),
     "te_evolve": (_I, [_P, _P, _P, _D, _D, _I, ctypes.POINTER(te_options), ctypes.POINTER(te_result), _P]),
@@ -286,6 +295,34 @@ def te_hamiltonian_create(row_ptr, col_idx, values, check_hermitian=False, strea
     h = _P()
     _check(_lib.te_hamiltonian_create(ctypes.byref(h), dim, nnz, *ptrs, flags, _stream(stream)))
     return Hamiltonian(h)
+
+
+def te_memory_burden_defaults(**overrides) -> te_memory_burden:
+    p = te_memory_burden()
+    _lib.te_memory_burden_defaults(ctypes.byref(p))
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+def te_hamiltonian_create_memory_burden(model=None, stream=None, **overrides):
+    """The paper's exemplary Hamiltonian built on the device; returns (Hamiltonian, index of
+    the initial state).  Parameters: a te_memory_burden, else the defaults with overrides."""
+    p = model if model is not None else te_memory_burden_defaults(**overrides)
+    h, idx = _P(), _I64()
+    _check(_lib.te_hamiltonian_create_memory_burden(ctypes.byref(h), ctypes.byref(p), ctypes.byref(idx),
+                                                    _stream(stream)))
+    return Hamiltonian(h), idx.value
+
+
+def te_hamiltonian_copy_csr(H: Hamiltonian, stream=None):
+    """Host copies (row_ptr int32, col int32, values complex128) of the handle's matrix."""
+    rp = np.empty(H.dim + 1, dtype=np.int32)
+    ci = np.empty(H.nnz, dtype=np.int32)
+    va = np.empty(H.nnz, dtype=np.complex128)
+    _check(_lib.te_hamiltonian_copy_csr(H.handle, ctypes.c_void_p(rp.ctypes.data), ctypes.c_void_p(ci.ctypes.data),
+                                        ctypes.c_void_p(va.ctypes.data), 0, _stream(stream)))
+    return rp, ci, va
 
 
 def te_evolve(H: Hamiltonian, v0, t: float, tol: float, m: int, options=None, out=None, stream=None):
