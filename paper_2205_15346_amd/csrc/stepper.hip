@@ -26,6 +26,14 @@ constexpr int kMaxTpn = 8;                       // threads sharing one quadratu
 
 struct StepShared {
     double Qt[kMaxM * 64];  // eigenvectors: column n (eigenvalue n) at Qt[n * 64 + row]
+    // divide and conquer: halves' inputs, merge arrays (sorted poles, kept poles, roots)
+    double U[kMaxM * 64];   // eigenvectors of the rank-one problem, U[j * 64 + i]
+    double dca[kMaxM], dcb[kMaxM], dd[kMaxM], dz[kMaxM], ds[kMaxM], zs[kMaxM];
+    double dk[kMaxM], zk[kMaxM], zh[kMaxM], tau[kMaxM];
+    double rc[kMaxM], rs[kMaxM];
+    int perm[kMaxM], keep[kMaxM], org[kMaxM], r1[kMaxM], r2[kMaxM], defl[kMaxM];
+    int dc_ok[2], dc_K, dc_nrot;
+    double dc_rho;
     double gx[kMaxM], gw[kMaxM];  // Gauss-Legendre nodes and weights on [-1, 1] (fast option)
     double d[kMaxM], e[kMaxM];
     double lam[kMaxM], cf[kMaxM];
@@ -43,6 +51,12 @@ __device__ __forceinline__ double rsqrt_nr(double t) {
     return y * fma(-0.5 * t * y, y, 1.5);
 }
 
+// 1/x: hardware estimate refined by one Newton step (relative error ~1 ulp).
+__device__ __forceinline__ double rcp_nr(double x) {
+    const double y = __builtin_amdgcn_rcp(x);
+    return y * fma(-x, y, 2.0);
+}
+
 // Value of a wave-distributed register array at a wave-uniform lane index.
 __device__ __forceinline__ double lane_get(double x, int i) {
     const long long v = __double_as_longlong(x);
@@ -58,7 +72,7 @@ __device__ __forceinline__ double lane_get(double x, int i) {
 // holds the eigenvalues (unsorted) and Qt[n * 64 + q] = Q[q][n].  False if an eigenvalue needed
 // more than 64 iterations.
 __device__ bool tridiag_ql(int k, const double* a, const double* b, double* lam, double* Qt) {
-    const int lane = threadIdx.x;  // < 64
+    const int lane = threadIdx.x & 63;  // run by one whole wave
     double dr = (lane < k) ? a[lane] : 0.0;
     double er = (lane < k - 1) ? b[lane] : 0.0;
     for (int c = 0; c < k; ++c) Qt[c * 64 + lane] = (lane == c) ? 1.0 : 0.0;
@@ -130,6 +144,290 @@ __device__ bool tridiag_ql(int k, const double* a, const double* b, double* lam,
     }
     if (lane < k) lam[lane] = dr;
     return ok;
+}
+
+// sum over the 4 lanes of a quad (lanes 4q..4q+3)
+__device__ __forceinline__ double quad_sum(double v) {
+    v += __shfl_xor(v, 1);
+    return v + __shfl_xor(v, 2);
+}
+
+// Root i of the secular equation 1 + rho sum_j z_j^2 / (d_j - lam) = 0 over the K kept poles
+// d (ascending, rho > 0): lam in (d_i, d_{i+1}), the last in (d_{K-1}, d_{K-1} + rho sum z^2),
+// solved by the 4 lanes of a quad (lane part = 0..3 sums terms j = part, part + 4, ...; every
+// lane then takes the same steps).  Coordinates are shifted to the nearer pole (chosen by the
+// sign at the midpoint), so d_j - lam is formed as (d_j - d_org) - tau without cancellation.
+// Iteration of Bunch, Nielsen and Sorensen: the sums over the poles below and above the root are
+// each replaced by one pole plus a constant matching value and slope at the iterate, and the
+// resulting quadratic is solved; bisection of the bracket when its root falls outside.  Stops
+// when the secular function is at its rounding level.  Returns tau; *org receives the origin.
+__device__ double secular_root(int i, int part, int K, const double* d, const double* z, double rho, int* org) {
+    const bool last = i == K - 1;
+    double lo, hi;
+    int o;
+    if (!last) {
+        const double mid = 0.5 * (d[i] + d[i + 1]);
+        double f = 0.0;
+        for (int j = part; j < K; j += 4) f += z[j] * z[j] * rcp_nr(d[j] - mid);
+        f = 1.0 + rho * quad_sum(f);
+        if (f >= 0.0) {
+            o = i;
+            lo = 0.0;
+            hi = mid - d[i];
+        } else {
+            o = i + 1;
+            lo = mid - d[i + 1];
+            hi = 0.0;
+        }
+    } else {
+        o = K - 1;
+        double s2 = 0.0;
+        for (int j = part; j < K; j += 4) s2 += z[j] * z[j];
+        lo = 0.0;
+        hi = rho * quad_sum(s2);
+    }
+    const double dorg = d[o];
+    const double di = d[i] - dorg, dn = last ? 0.0 : d[i + 1] - dorg;
+    double tau = 0.5 * (lo + hi);
+    for (int it = 0; it < 64; ++it) {
+        double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0;
+        for (int j = part; j < K; j += 4) {
+            const double r = rcp_nr((d[j] - dorg) - tau);
+            const double w = z[j] * z[j] * r;
+            if (j <= i) {
+                psi += w;
+                dpsi += w * r;
+            } else {
+                phi += w;
+                dphi += w * r;
+            }
+        }
+        psi = quad_sum(psi);
+        dpsi = quad_sum(dpsi);
+        phi = quad_sum(phi);
+        dphi = quad_sum(dphi);
+        const double f = 1.0 + rho * (psi + phi);
+        if (fabs(f) <= 2.0 * kEps * (1.0 + rho * (fabs(psi) + fabs(phi)))) break;
+        if (f < 0.0) lo = tau;
+        else hi = tau;
+        const double Q = dpsi * (di - tau) * (di - tau);
+        const double P = psi - Q / (di - tau);
+        double nt;
+        if (!last) {
+            const double S = dphi * (dn - tau) * (dn - tau);
+            const double R = phi - S / (dn - tau);
+            const double c = 1.0 + rho * (P + R);
+            const double a2 = c;
+            const double a1 = -c * (di + dn) - rho * (Q + S);
+            const double a0 = c * di * dn + rho * (Q * dn + S * di);
+            const double sq = sqrt(fmax(a1 * a1 - 4.0 * a2 * a0, 0.0));
+            double x1, x2;
+            if (a1 <= 0.0) {
+                x1 = (a2 != 0.0) ? (-a1 + sq) / (2.0 * a2) : HUGE_VAL;
+                x2 = (-a1 + sq != 0.0) ? 2.0 * a0 / (-a1 + sq) : HUGE_VAL;
+            } else {
+                x1 = (-a1 - sq != 0.0) ? 2.0 * a0 / (-a1 - sq) : HUGE_VAL;
+                x2 = (a2 != 0.0) ? (-a1 - sq) / (2.0 * a2) : HUGE_VAL;
+            }
+            if (x1 > lo && x1 < hi) nt = x1;
+            else if (x2 > lo && x2 < hi) nt = x2;
+            else nt = 0.5 * (lo + hi);
+        } else {
+            const double c = 1.0 + rho * P;
+            nt = (c != 0.0) ? di + rho * Q / c : 0.5 * (lo + hi);
+            if (!(nt > lo && nt < hi)) nt = 0.5 * (lo + hi);
+        }
+        if (nt == tau || fabs(nt - tau) <= 2.0 * kEps * fabs(nt)) {
+            tau = nt;
+            break;
+        }
+        tau = nt;
+    }
+    *org = o;
+    return tau;
+}
+
+// Divide and conquer (Cuppen) on the k x k symmetric tridiagonal, run by the whole workgroup:
+// T = diag(T1', T2') + rho v v^T with v = e_m + sign(beta) e_{m+1}, rho = |beta| (beta the
+// coupling of the halves, removed from their touching diagonal entries).  Waves 0 and 1 solve
+// T1' and T2' by QL at the same time; the merge solves D + rho z z^T, z = [last row of Q1;
+// sign(beta) first row of Q2]: poles sorted, deflation (a negligible z component, or two poles
+// close enough that a rotation zeroes one z component, LAPACK's criteria), one secular root
+// per thread, the z of Gu and Eisenstat recomputed from the roots (orthogonal eigenvectors by
+// construction), and the rank-one problem's eigenvectors applied to the halves' ones in place,
+// one component per wave.  Output as for tridiag_ql (eigenvalues unsorted).  False if a half's
+// QL failed.
+__device__ bool tridiag_dc(int k, const double* a, const double* b, double* lam, StepShared& sh) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m = k / 2, k2 = k - m;
+    const double beta = b[m - 1];
+    const double rho0 = fabs(beta), sg = beta >= 0.0 ? 1.0 : -1.0;
+    double* Qt = sh.Qt;
+    if (tid < k) sh.dca[tid] = a[tid] - ((tid == m - 1 || tid == m) ? rho0 : 0.0);
+    if (tid < k - 1) sh.dcb[tid] = (tid == m - 1) ? 0.0 : b[tid];
+    __syncthreads();
+    if (wave == 0) {
+        const bool o = tridiag_ql(m, sh.dca, sh.dcb, sh.lam, Qt);
+        if (lane == 0) sh.dc_ok[0] = o ? 1 : 0;
+    } else if (wave == 1) {
+        const bool o = tridiag_ql(k2, sh.dca + m, sh.dcb + m, sh.lam + m, Qt + m * 64);
+        if (lane == 0) sh.dc_ok[1] = o ? 1 : 0;
+    }
+    __syncthreads();
+    if (!sh.dc_ok[0] || !sh.dc_ok[1]) return false;
+    // second half's vectors to global components: x -> x + m (one row per wave at a time)
+    for (int n = m + wave; n < k; n += kWaves) {
+        const double v = Qt[n * 64 + lane];
+        const double sft = __shfl(v, (lane - m) & 63);
+        Qt[n * 64 + lane] = (lane >= m && lane < k) ? sft : 0.0;
+    }
+    __syncthreads();
+    if (tid < k) {
+        sh.dd[tid] = sh.lam[tid];
+        sh.dz[tid] = (tid < m) ? Qt[tid * 64 + m - 1] : sg * Qt[tid * 64 + m];
+    }
+    __syncthreads();
+    if (tid < k) {  // rank sort of the poles (ties by index)
+        const double dn = sh.dd[tid];
+        int r = 0;
+        for (int j = 0; j < k; ++j) r += (sh.dd[j] < dn || (sh.dd[j] == dn && j < tid)) ? 1 : 0;
+        sh.perm[r] = tid;
+    }
+    __syncthreads();
+    if (tid < k) {
+        sh.ds[tid] = sh.dd[sh.perm[tid]];
+        sh.zs[tid] = sh.dz[sh.perm[tid]];
+    }
+    __syncthreads();
+    if (tid == 0) {  // normalisation and deflation, in sorted order
+        double nz2 = 0.0, dmax = 0.0;
+        for (int j = 0; j < k; ++j) {
+            nz2 += sh.zs[j] * sh.zs[j];
+            dmax = fmax(dmax, fabs(sh.ds[j]));
+        }
+        const double rho = rho0 * nz2, inv = 1.0 / sqrt(nz2);
+        for (int j = 0; j < k; ++j) sh.zs[j] *= inv;
+        const double tol = 8.0 * kEps * fmax(dmax, rho);
+        int K = 0, nrot = 0, lastj = -1;
+        for (int j = 0; j < k; ++j) {
+            sh.defl[j] = 0;
+            if (rho * fabs(sh.zs[j]) <= tol) {
+                sh.defl[j] = 1;
+                continue;
+            }
+            if (lastj >= 0) {
+                const double zl = sh.zs[lastj], zj = sh.zs[j];
+                const double r = hypot(zl, zj);
+                const double c = zj / r, s = -zl / r;
+                const double t = sh.ds[j] - sh.ds[lastj];
+                if (fabs(t * c * s) <= tol) {
+                    sh.zs[j] = r;
+                    sh.zs[lastj] = 0.0;
+                    const double dl = sh.ds[lastj], dj = sh.ds[j];
+                    sh.ds[lastj] = dl * c * c + dj * s * s;
+                    sh.ds[j] = dl * s * s + dj * c * c;
+                    sh.r1[nrot] = sh.perm[lastj];
+                    sh.r2[nrot] = sh.perm[j];
+                    sh.rc[nrot] = c;
+                    sh.rs[nrot] = s;
+                    ++nrot;
+                    sh.defl[lastj] = 1;
+                }
+            }
+            lastj = j;
+        }
+        for (int j = 0; j < k; ++j)
+            if (!sh.defl[j]) {
+                sh.keep[K] = j;
+                sh.dk[K] = sh.ds[j];
+                sh.zk[K] = sh.zs[j];
+                ++K;
+            }
+        sh.dc_K = K;
+        sh.dc_nrot = nrot;
+        sh.dc_rho = rho;
+    }
+    __syncthreads();
+    const int K = sh.dc_K;
+    const double rho = sh.dc_rho;
+    if (wave == 0) {  // deflation rotations, in order, on the vector rows
+        for (int q = 0; q < sh.dc_nrot; ++q) {
+            const int p1 = sh.r1[q], p2 = sh.r2[q];
+            const double c = sh.rc[q], s = sh.rs[q];
+            if (lane < k) {
+                const double vl = Qt[p1 * 64 + lane], vj = Qt[p2 * 64 + lane];
+                Qt[p1 * 64 + lane] = c * vl + s * vj;
+                Qt[p2 * 64 + lane] = -s * vl + c * vj;
+            }
+        }
+    }
+    // roots: root q on the quad of threads 4q..4q+3 (the quad's lanes stay together: K <= 64)
+    {
+        const int q = tid >> 2, part = tid & 3;
+        if (q < K) {
+            int o;
+            const double t = secular_root(q, part, K, sh.dk, sh.zk, rho, &o);
+            if (part == 0) {
+                sh.tau[q] = t;
+                sh.org[q] = o;
+            }
+        }
+    }
+    __syncthreads();
+    // per-root work below: root i on lane i / 4 of wave i % 4
+    const int ri = lane * kWaves + wave;
+    if (ri < K) {  // z recomputed from the roots: zh_j^2 = prod_i (lam_i - d_j) / prod_{i != j} (d_i - d_j) / rho
+        const double dj = sh.dk[ri];
+        double num = 1.0;
+        for (int i = 0; i < K; ++i) {
+            num *= (sh.dk[sh.org[i]] - dj) + sh.tau[i];
+            if (i != ri) num *= rcp_nr(sh.dk[i] - dj);
+        }
+        sh.zh[ri] = copysign(sqrt(fabs(num / rho)), sh.zk[ri]);
+    }
+    __syncthreads();
+    if (ri < K) {  // eigenvector ri of the rank-one problem: zh_j / (d_j - lam_ri), normalised
+        const double dorg = sh.dk[sh.org[ri]], t = sh.tau[ri];
+        double n2 = 0.0;
+        for (int j = 0; j < K; ++j) {
+            const double u = sh.zh[j] * rcp_nr((sh.dk[j] - dorg) - t);
+            sh.U[j * 64 + ri] = u;
+            n2 += u * u;
+        }
+        const double inv = rsqrt_nr(n2);
+        for (int j = 0; j < K; ++j) sh.U[j * 64 + ri] *= inv;
+    }
+    __syncthreads();
+    // kept vector rows <- (kept rows) U, component by component (component x on wave x % 4):
+    // lane j holds component x of kept row j, broadcast to all lanes by readlane
+    const int rowj = (lane < K) ? sh.perm[sh.keep[lane]] : 0;
+    for (int x = wave; x < k; x += kWaves) {
+        const double vj = (lane < K) ? Qt[rowj * 64 + x] : 0.0;
+        double acc = 0.0;
+#pragma unroll 4
+        for (int j = 0; j < K; ++j) acc = fma(lane_get(vj, j), sh.U[j * 64 + lane], acc);
+        if (lane < K) Qt[rowj * 64 + x] = acc;
+    }
+    if (tid < k) {
+        const int sj = tid;  // sorted position
+        if (sh.defl[sj]) lam[sh.perm[sj]] = sh.ds[sj];
+    }
+    if (ri < K) lam[sh.perm[sh.keep[ri]]] = sh.dk[sh.org[ri]] + sh.tau[ri];
+    __syncthreads();
+    return true;
+}
+
+// Eigen-decomposition of the tridiagonal (a, b) by the whole workgroup: divide and conquer from
+// k = 16 on, QL (wave 0) below it or should a half fail.
+__device__ bool tridiag_eig(int k, const double* a, const double* b, double* lam, StepShared& sh) {
+    __shared__ int ok_sh;
+    if (k >= 16 && tridiag_dc(k, a, b, lam, sh)) return true;
+    if (threadIdx.x < 64) {
+        const bool q = tridiag_ql(k, a, b, lam, sh.Qt);
+        if (threadIdx.x == 0) ok_sh = q ? 1 : 0;
+    }
+    __syncthreads();
+    return ok_sh != 0;
 }
 
 // ------------------------------------------------------------------------- quadrature
@@ -439,15 +737,10 @@ __device__ bool prepare_spectrum(const DevState* st, int k, StepShared& sh) {
         sh.e[tid] = (tid < k - 1) ? st->beta[tid] : 0.0;
     }
     __syncthreads();
-    __shared__ int ok_sh;
-    if (tid < 64) {
-        const bool ok = tridiag_ql(k, sh.d, sh.e, sh.lam, sh.Qt);
-        if (tid == 0) ok_sh = ok ? 1 : 0;
-    }
-    __syncthreads();
+    const bool ok = tridiag_eig(k, sh.d, sh.e, sh.lam, sh);
     if (tid < k) sh.cf[tid] = sh.Qt[tid * 64 + k - 1] * sh.Qt[tid * 64];
     __syncthreads();
-    return ok_sh != 0;
+    return ok;
 }
 
 // omega_i = sum_n Q[i][n] exp(-i lam_n tau) Q[0][n], scaled by s_i for the raw columns
@@ -630,11 +923,8 @@ __global__ __launch_bounds__(kBlock) void k_eig_only(int k, const double* alpha,
         sh.e[tid] = (tid < k - 1) ? beta[tid] : 0.0;
     }
     __syncthreads();
-    if (tid < 64) {
-        const bool ok = tridiag_ql(k, sh.d, sh.e, sh.lam, sh.Qt);
-        if (tid == 0) *status = ok ? 0 : 1;
-    }
-    __syncthreads();
+    const bool ok = tridiag_eig(k, sh.d, sh.e, sh.lam, sh);
+    if (tid == 0) *status = ok ? 0 : 1;
     if (tid < k) {
         lambda[tid] = sh.lam[tid];
         for (int n = 0; n < k; ++n) Q[n * k + tid] = sh.Qt[n * 64 + tid];  // column-major
