@@ -110,6 +110,24 @@ def _tridiag_cases():
     cases["tiny_beta"] = (rng.uniform(-1, 1, 30), np.full(29, 1e-9))
     cases["graded"] = (np.logspace(-8, 2, 40), np.logspace(-6, 1, 39))
     cases["constant"] = (np.full(16, 0.5), np.full(15, 1.0))
+    # divide and conquer (k >= 16) splits at k // 2: coupling there exactly zero, tiny, negative;
+    # identical halves (pairs of equal poles: rotation deflation); sizes around the switch
+    b = rng.uniform(0.1, 2, 39)
+    b[19] = 0.0
+    cases["split_zero"] = (rng.uniform(-3, 3, 40), b)
+    b = rng.uniform(0.1, 2, 39)
+    b[19] = 1e-300
+    cases["split_tiny"] = (rng.uniform(-3, 3, 40), b)
+    cases["negative_beta"] = (rng.uniform(-3, 3, 40), -rng.uniform(0.1, 2, 39))
+    h, e = rng.uniform(-3, 3, 20), rng.uniform(0.1, 2, 19)
+    cases["equal_halves"] = (np.r_[h, h], np.r_[e, 1e-3, e])
+    cases["zero_diagonal"] = (np.zeros(40), np.ones(39))
+    cases["wide_range"] = (rng.uniform(-1e6, 1e6, 40), rng.uniform(1e-3, 1.0, 39))
+    for k in (15, 17, 63):
+        cases[f"rand{k}"] = (rng.uniform(-3, 3, k), rng.uniform(0.1, 2, k - 1))
+    H, v0 = W.xxz_chain(12, seed=2)
+    ar = O.arnoldi(H, v0, 40, 1e-300)
+    cases["lanczos_xxz12"] = ((1j * ar.M.diagonal()).real, ar.M.diagonal(-1).real)
     return cases
 
 
