@@ -63,8 +63,8 @@ enum {
 #define TE_CHECK_HERMITIAN 2u /* verify H == H^H on the device (needs sorted columns) */
 #define TE_STORE_COMPLEX 4u   /* keep 16-byte complex entries even when all are real */
 
-#define TE_MAX_KRYLOV 64 /* largest Krylov dimension m: the small eigenproblem runs in one
-                            64-lane wavefront */
+#define TE_MAX_KRYLOV 64 /* largest Krylov dimension m: a row of the small eigenproblem is held
+                            by one 64-lane wavefront */
 
 /* Tunable constants of the step-size search (Alg. 1 step 2).  te_default_options()
  * fills: n_substeps=10, t_init=0.1, shrink=0.97, quad_rel_tol=1e-3, quad_max_level=15,
@@ -304,7 +304,8 @@ te_status te_arnoldi(te_hamiltonian h, const te_c128* u, int32_t m, double tol_r
  * J = Q diag(lambda) Q^T for the k x k real symmetric tridiagonal with diagonal alpha[k]
  * and off-diagonal beta[k-1].  Host arrays in/out; Q is column-major k*k (column n is the
  * eigenvector of lambda[n]); eigenvalues are not sorted.  Runs on the device in one
- * wavefront.  1 <= k <= TE_MAX_KRYLOV.  Synchronous. */
+ * workgroup (divide and conquer from k = 16, implicit QL below), the same code the step kernel
+ * of te_evolve runs.  1 <= k <= TE_MAX_KRYLOV.  Synchronous. */
 te_status te_tridiag_eig(int32_t k, const double* alpha, const double* beta, double* lambda,
                          double* Q, void* stream);
 
