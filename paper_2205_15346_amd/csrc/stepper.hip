@@ -33,7 +33,7 @@ struct StepShared {
     double rc[kMaxM], rs[kMaxM];
     int perm[kMaxM], keep[kMaxM], org[kMaxM], r1[kMaxM], r2[kMaxM], defl[kMaxM];
     int dc_ok[2], dc_K, dc_nrot;
-    double dc_rho;
+    double dc_rho, dc_tol;
     double gx[kMaxM], gw[kMaxM];  // Gauss-Legendre nodes and weights on [-1, 1] (fast option)
     double d[kMaxM], e[kMaxM];
     double lam[kMaxM], cf[kMaxM];
@@ -299,24 +299,30 @@ __device__ bool tridiag_dc(int k, const double* a, const double* b, double* lam,
         sh.zs[tid] = sh.dz[sh.perm[tid]];
     }
     __syncthreads();
-    if (tid == 0) {  // normalisation and deflation, in sorted order
-        double nz2 = 0.0, dmax = 0.0;
-        for (int j = 0; j < k; ++j) {
-            nz2 += sh.zs[j] * sh.zs[j];
-            dmax = fmax(dmax, fabs(sh.ds[j]));
+    {  // normalisation: ||z||^2 and max |d| over the block
+        const double z2 = (tid < k) ? sh.zs[tid] * sh.zs[tid] : 0.0;
+        const double da = (tid < k) ? fabs(sh.ds[tid]) : 0.0;
+        const double nz2 = block_sum(z2, sh.red);
+        const double dmax = block_max(da, sh.red + kWaves);
+        if (tid < k) sh.zs[tid] *= rsqrt_nr(nz2);
+        if (tid == 0) {
+            sh.dc_rho = rho0 * nz2;
+            sh.dc_tol = 8.0 * kEps * fmax(dmax, rho0 * nz2);
         }
-        const double rho = rho0 * nz2, inv = 1.0 / sqrt(nz2);
-        for (int j = 0; j < k; ++j) sh.zs[j] *= inv;
-        const double tol = 8.0 * kEps * fmax(dmax, rho);
-        int K = 0, nrot = 0, lastj = -1;
+    }
+    __syncthreads();
+    if (tid == 0) {  // deflation in sorted order (each pair test depends on the previous kept pole)
+        const double rho = sh.dc_rho, tol = sh.dc_tol;
+        int nrot = 0, lastj = -1;
         for (int j = 0; j < k; ++j) {
-            sh.defl[j] = 0;
-            if (rho * fabs(sh.zs[j]) <= tol) {
+            const double zj = sh.zs[j];
+            if (rho * fabs(zj) <= tol) {
                 sh.defl[j] = 1;
                 continue;
             }
+            sh.defl[j] = 0;
             if (lastj >= 0) {
-                const double zl = sh.zs[lastj], zj = sh.zs[j];
+                const double zl = sh.zs[lastj];
                 const double r = hypot(zl, zj);
                 const double c = zj / r, s = -zl / r;
                 const double t = sh.ds[j] - sh.ds[lastj];
@@ -336,16 +342,20 @@ __device__ bool tridiag_dc(int k, const double* a, const double* b, double* lam,
             }
             lastj = j;
         }
-        for (int j = 0; j < k; ++j)
-            if (!sh.defl[j]) {
-                sh.keep[K] = j;
-                sh.dk[K] = sh.ds[j];
-                sh.zk[K] = sh.zs[j];
-                ++K;
-            }
-        sh.dc_K = K;
         sh.dc_nrot = nrot;
-        sh.dc_rho = rho;
+    }
+    __syncthreads();
+    if (tid < k && !sh.defl[tid]) {  // compaction of the kept poles, in sorted order
+        int pos = 0;
+        for (int j = 0; j < tid; ++j) pos += sh.defl[j] ? 0 : 1;
+        sh.keep[pos] = tid;
+        sh.dk[pos] = sh.ds[tid];
+        sh.zk[pos] = sh.zs[tid];
+    }
+    if (tid == 0) {
+        int K = 0;
+        for (int j = 0; j < k; ++j) K += sh.defl[j] ? 0 : 1;
+        sh.dc_K = K;
     }
     __syncthreads();
     const int K = sh.dc_K;

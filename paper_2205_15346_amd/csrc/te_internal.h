@@ -195,6 +195,19 @@ __device__ __forceinline__ double block_sum(double v, double* lds /* kWaves */) 
     return s;
 }
 
+// Block-wide maximum; every thread gets the result.
+__device__ __forceinline__ double block_max(double v, double* lds /* kWaves */) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    __syncthreads();
+    if (lane == 0) lds[wave] = v;
+    __syncthreads();
+    double s = lds[0];
+    for (int w = 1; w < kWaves; ++w) s = fmax(s, lds[w]);
+    return s;
+}
+
 // ----------------------------------------------------------------------- launchers
 struct Workspace;  // defined in api.hip
 
