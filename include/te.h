@@ -193,10 +193,28 @@ void te_memory_burden_defaults(te_memory_burden* p);
 /* Builds the matrix in device memory and returns its handle; *initial_index (may be NULL)
  * receives the basis index of the initial state of eq. initialStateSimple
  * (n_0 = N_0, a_1..a_{N_m} occupied).  TE_ERR_INVALID_ARG for parameters out of range,
- * TE_ERR_UNSUPPORTED when dim or nnz does not fit int32 or a row exceeds 512 entries.
- * Synchronous. */
+ * TE_ERR_UNSUPPORTED when dim exceeds 2^26, nnz does not fit int32 or a row exceeds 512
+ * entries.  Synchronous. */
 te_status te_hamiltonian_create_memory_burden(te_hamiltonian* out, const te_memory_burden* p,
                                               int64_t* initial_index, void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Open Bose chain of K modes with N bosons built on the device, in the number-state basis of
+ * Sec. "Creation of Hamiltonian Matrix" (eqs. basisState, totalOccupationNumber):
+ *   H = sum_{k<K-1} ( hop[k] b_k^+ b_{k+1} + conj(hop[k]) b_{k+1}^+ b_k ) + sum_k U[k] n_k (n_k - 1).
+ * Basis: all (n_0..n_{K-1}) with sum N in descending lexicographic order, index 0 =
+ * (N, 0, ..., 0).  The index of a state and its inverse (eq. findIndices) are closed forms of
+ * the combinatorial number system; no basis, lookup table or triplet list is built.  Every row
+ * stores its diagonal (also when zero) and its hops, columns ascending.
+ *   K    : 1..64 modes;  N : 0..65535 bosons;  dim = binom(N + K - 1, K - 1) <= 2^26.
+ *   U    : host double[K], finite.
+ *   hop  : host te_c128[K - 1], finite (may be NULL when K == 1).
+ *   flags: 0 or TE_STORE_COMPLEX (as for te_hamiltonian_create: without it a matrix whose
+ *          hops are all real keeps 8-byte entries).
+ * TE_ERR_INVALID_ARG for arguments out of range, TE_ERR_UNSUPPORTED when dim exceeds 2^26 or
+ * nnz does not fit int32.  Synchronous on `stream`. */
+te_status te_hamiltonian_create_bose_chain(te_hamiltonian* out, int32_t K, int32_t N, const double* U,
+                                          const te_c128* hop, uint32_t flags, void* stream);
 te_status te_hamiltonian_destroy(te_hamiltonian h); /* frees everything the handle owns */
 te_status te_hamiltonian_info(te_hamiltonian h, int64_t* dim, int64_t* nnz, double* norm1);
 

@@ -519,6 +519,20 @@ static te_status validate_handle(te_hamiltonian h, int check_hermitian, int* err
     return TE_OK;
 }
 
+// Every imaginary part is zero: keep the real parts only (8-byte entries).
+static te_status keep_real_entries(te_hamiltonian h, hipStream_t s) {
+    const int64_t nnz = h->csr.nnz;
+    h->rval = (double*)dev_alloc((size_t)nnz * sizeof(double));
+    if (!h->rval) return fail(TE_ERR_OUT_OF_MEMORY, "device allocation for the real entries failed");
+    TE_HIP(launch_real_part(h->val, h->rval, nnz, s));
+    TE_HIP(hipStreamSynchronize(s));
+    dev_free(h->val);
+    h->val = nullptr;
+    h->csr.val = nullptr;
+    h->csr.rval = h->rval;
+    return TE_OK;
+}
+
 te_status te_hamiltonian_create(te_hamiltonian* out, int64_t dim, int64_t nnz, const int32_t* row_ptr,
                                 const int32_t* col_idx, const te_c128* values, uint32_t flags, void* stream) {
     if (!out || !row_ptr || !col_idx || !values) return fail(TE_ERR_INVALID_ARG, "null pointer");
@@ -561,19 +575,7 @@ te_status te_hamiltonian_create(te_hamiltonian* out, int64_t dim, int64_t nnz, c
     if (rc == TE_OK) rc = validate_handle(h, (flags & TE_CHECK_HERMITIAN) ? 1 : 0, err, rowsum, &herr, s);
     dev_free(rowsum);
     dev_free(err);
-    if (rc == TE_OK && !(herr & 32) && !(flags & TE_STORE_COMPLEX)) {
-        // every imaginary part is zero: keep the real parts only
-        h->rval = (double*)dev_alloc(nnz * sizeof(double));
-        if (!h->rval) rc = fail(TE_ERR_OUT_OF_MEMORY, "device allocation for the real entries failed");
-        if (rc == TE_OK) chk(launch_real_part(h->val, h->rval, nnz, s), "real part");
-        if (rc == TE_OK) chk(hipStreamSynchronize(s), "hipStreamSynchronize");
-        if (rc == TE_OK) {
-            dev_free(h->val);
-            h->val = nullptr;
-            h->csr.val = nullptr;
-            h->csr.rval = h->rval;
-        }
-    }
+    if (rc == TE_OK && !(herr & 32) && !(flags & TE_STORE_COMPLEX)) rc = keep_real_entries(h, s);
     if (rc != TE_OK) {
         delete h;
         return rc;
@@ -666,7 +668,8 @@ te_status te_hamiltonian_create_memory_burden(te_hamiltonian* out, const te_memo
     if (C > ((int64_t)1 << 31) / (P.N0 + 1)) return fail(TE_ERR_UNSUPPORTED, "dimension does not fit int32");
     const int64_t dim = C * (P.N0 + 1);
     const int64_t nnz = C * ((int64_t)(P.N0 + 1) * (1 + Q) + 2 * (int64_t)P.N0);
-    if (dim >= ((int64_t)1 << 31) - 1 || nnz >= ((int64_t)1 << 31)) return fail(TE_ERR_UNSUPPORTED, "nnz does not fit int32");
+    if (dim > kMaxModelRows || nnz >= ((int64_t)1 << 31))
+        return fail(TE_ERR_UNSUPPORTED, "more than 2^26 rows, or nnz that does not fit int32");
     int slots = 1;
     while (slots < max_len) slots <<= 1;
     if (slots > 512) return fail(TE_ERR_UNSUPPORTED, "a row would exceed 512 entries");
@@ -748,6 +751,100 @@ te_status te_hamiltonian_create_memory_burden(te_hamiltonian* out, const te_memo
         return rc;
     }
     if (initial_index) *initial_index = 0;  // n_0 = N_0 (block 0) and the first configuration
+    *out = h;
+    return TE_OK;
+}
+
+te_status te_hamiltonian_create_bose_chain(te_hamiltonian* out, int32_t K, int32_t N, const double* U,
+                                          const te_c128* hop, uint32_t flags, void* stream) {
+    if (!out || !U || (K > 1 && !hop)) return fail(TE_ERR_INVALID_ARG, "null pointer");
+    *out = nullptr;
+    if (K < 1 || K > 64 || N < 0 || N > 65535) return fail(TE_ERR_INVALID_ARG, "need 1 <= K <= 64 and 0 <= N <= 65535");
+    if (flags & ~TE_STORE_COMPLEX) return fail(TE_ERR_INVALID_ARG, "unknown flags");
+    for (int k = 0; k < K; ++k)
+        if (!std::isfinite(U[k]) || (k < K - 1 && (!std::isfinite(hop[k].re) || !std::isfinite(hop[k].im))))
+            return fail(TE_ERR_INVALID_ARG, "non-finite parameter");
+    // binomials C(a, b), a <= N + K, b <= K, saturated (entries beyond the dimension are never used)
+    const int bw = K + 1, rows = N + K + 1;
+    const int64_t cap = (int64_t)1 << 61;  // the sum of two saturated entries stays in range
+    std::vector<int64_t> binom((size_t)rows * bw, 0);
+    for (int a = 0; a < rows; ++a) {
+        binom[(size_t)a * bw] = 1;
+        for (int b = 1; b <= std::min(a, K); ++b) {
+            const int64_t x = binom[(size_t)(a - 1) * bw + b - 1] + (b <= a - 1 ? binom[(size_t)(a - 1) * bw + b] : 0);
+            binom[(size_t)a * bw + b] = std::min(x, cap);
+        }
+    }
+    const int64_t dim = binom[(size_t)(N + K - 1) * bw + (K - 1)];  // compositions of N into K parts
+    if (dim > kMaxModelRows) return fail(TE_ERR_UNSUPPORTED, "more than 2^26 rows");
+    int slots = 1;
+    while (slots < 2 * K - 1) slots <<= 1;
+    hipStream_t s = (hipStream_t)stream;
+    auto* h = new (std::nothrow) te_hamiltonian_s();
+    if (!h) return fail(TE_ERR_OUT_OF_MEMORY, "host allocation failed");
+    const int64_t nb = (dim + 4 * kBlock - 1) / (4 * kBlock);
+    h->row_ptr = (int*)dev_alloc((size_t)(dim + 1) * sizeof(int));
+    int* cnt = (int*)dev_alloc((size_t)dim * sizeof(int));
+    int64_t* scratch = (int64_t*)dev_alloc((size_t)(nb + 2) * sizeof(int64_t));
+    int64_t* d_binom = (int64_t*)dev_alloc(binom.size() * sizeof(int64_t));
+    double* d_U = (double*)dev_alloc((size_t)K * sizeof(double));
+    double2* d_hop = (double2*)dev_alloc((size_t)std::max(K - 1, 1) * sizeof(double2));
+    double* rowsum = (double*)dev_alloc((size_t)dim * sizeof(double) + 64);
+    int* err = (int*)dev_alloc(64);
+    auto cleanup = [&]() {
+        dev_free(cnt);
+        dev_free(scratch);
+        dev_free(d_binom);
+        dev_free(d_U);
+        dev_free(d_hop);
+        dev_free(rowsum);
+        dev_free(err);
+    };
+    if (!h->row_ptr || !cnt || !scratch || !d_binom || !d_U || !d_hop || !rowsum || !err) {
+        cleanup();
+        delete h;
+        return fail(TE_ERR_OUT_OF_MEMORY, "device allocation for the matrix failed");
+    }
+    BoseChainDev B;
+    B.K = K;
+    B.N = N;
+    B.slots = slots;
+    B.dim = dim;
+    B.bw = bw;
+    B.binom = d_binom;
+    B.U = d_U;
+    B.hop = d_hop;
+    te_status rc = TE_OK;
+    int64_t nnz = 0;
+    hipError_t e = hipMemcpyAsync(d_binom, binom.data(), binom.size() * sizeof(int64_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_U, U, (size_t)K * sizeof(double), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && K > 1) e = hipMemcpyAsync(d_hop, hop, (size_t)(K - 1) * sizeof(double2), hipMemcpyHostToDevice, s);
+    // the column and value arrays are sized by the counted entries: count + scan, then fill
+    if (e == hipSuccess) e = launch_bose_row_ptr(B, h->row_ptr, cnt, scratch, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&nnz, scratch + nb, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess && nnz >= ((int64_t)1 << 31)) rc = fail(TE_ERR_UNSUPPORTED, "nnz does not fit int32");
+    if (e == hipSuccess && rc == TE_OK) {
+        h->col = (int*)dev_alloc((size_t)nnz * sizeof(int));
+        h->val = (double2*)dev_alloc((size_t)nnz * sizeof(double2));
+        if (!h->col || !h->val) rc = fail(TE_ERR_OUT_OF_MEMORY, "device allocation for the matrix failed");
+    }
+    if (e == hipSuccess && rc == TE_OK) e = launch_bose_fill(B, h->row_ptr, h->col, h->val, s);
+    if (e != hipSuccess && rc == TE_OK) rc = fail(TE_ERR_DEVICE, std::string("building the matrix: ") + hipGetErrorString(e));
+    h->csr.row_ptr = h->row_ptr;
+    h->csr.col = h->col;
+    h->csr.val = h->val;
+    h->csr.rval = nullptr;
+    h->csr.dim = (int)dim;
+    h->csr.nnz = nnz;
+    int herr = 0;
+    if (rc == TE_OK) rc = validate_handle(h, 1, err, rowsum, &herr, s);
+    cleanup();
+    if (rc == TE_OK && !(herr & 32) && !(flags & TE_STORE_COMPLEX)) rc = keep_real_entries(h, s);
+    if (rc != TE_OK) {
+        delete h;
+        return rc;
+    }
     *out = h;
     return TE_OK;
 }

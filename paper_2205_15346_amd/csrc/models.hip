@@ -181,7 +181,234 @@ __global__ __launch_bounds__(kBlock) void k_model_fill(ModelArgs A, int* __restr
     }
 }
 
+// ------------------------------------------------------------------------ Bose chain
+// Fock states |n_1..n_K> with sum n_k = N (Sec. "Creation of Hamiltonian Matrix", eqs.
+// basisState and totalOccupationNumber) in descending lexicographic order.  The index map and
+// its inverse (eq. findIndices) are closed forms of the combinatorial number system instead of
+// a hash table: with R_i = N - sum_{l<i} n_l, rank = sum_i comp(R_i - n_i - 1, K - i), where
+// comp(s, m) = binom(s + m - 1, m - 1) counts the compositions of s into m parts (the states
+// that agree up to i and hold more bosons in mode i).  A hop between modes k and k + 1 changes
+// only the terms i = k, k + 1 of that sum, so the partner's rank is the row's own rank plus or
+// minus one comp() term.
+struct BoseArgs {
+    int K, N;
+    int slots;             // power of two >= 2K - 1
+    int64_t dim;
+    int bw;                // row stride of the binomial table
+    const int64_t* binom;  // binom[a * bw + b], a <= N + K, b <= K
+    const double* U;       // on-site interaction U_k n_k (n_k - 1)
+    const double2* hop;    // a_k of a_k b_k^+ b_{k+1} + conj(a_k) b_{k+1}^+ b_k
+};
+
+__device__ __forceinline__ int64_t comp(const BoseArgs& A, int s, int m) {
+    if (m == 0) return s == 0 ? 1 : 0;
+    if (s < 0) return 0;
+    return A.binom[(int64_t)(s + m - 1) * A.bw + (m - 1)];
+}
+
+// occupation of mode i of the state of rank `rank` (lanes = modes; every lane runs the same walk
+// and keeps its own mode), and R_i = bosons left for modes i..K-1.  Within the block of states
+// that agree before mode i, comp(R_i - v - 1, K - i) of them hold more than v bosons in mode i,
+// a count that falls as v grows: n_i is the smallest v whose count does not exceed the rank left,
+// found by bisection, so a row costs O(K log N) table reads.
+__device__ void bose_unrank(const BoseArgs& A, int64_t rank, int lane, int* n_lane, int* R_lane) {
+    int R = A.N, mine = 0, mineR = 0;
+    for (int i = 0; i < A.K; ++i) {
+        const int m = A.K - i;
+        int lo = 0, hi = R;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (comp(A, R - mid - 1, m) <= rank)
+                hi = mid;
+            else
+                lo = mid + 1;
+        }
+        rank -= comp(A, R - lo - 1, m);
+        if (lane == i) {
+            mine = lo;
+            mineR = R;
+        }
+        R -= lo;
+    }
+    *n_lane = mine;
+    *R_lane = mineR;
+}
+
+// entries per row: diagonal + a hop out of each occupied mode to each neighbour
+__global__ __launch_bounds__(kBlock) void k_bose_count(BoseArgs A, int* __restrict__ cnt) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t r = (int64_t)blockIdx.x * kRowsPerBlock + w;
+    if (r >= A.dim) return;
+    int n, R;
+    bose_unrank(A, r, lane, &n, &R);
+    const bool occ = lane < A.K && n > 0;
+    const unsigned long long m = __ballot(occ);
+    const int nz = __popcll(m);
+    if (lane == 0) cnt[r] = 1 + 2 * nz - (int)(m & 1ull) - (int)((m >> (A.K - 1)) & 1ull);
+}
+
+// exclusive scan of the row counts into row_ptr: per-block scans of 1024 rows, a scan of the
+// block totals, and the block offsets added back
+constexpr int kScanRows = 4 * kBlock;
+
+__global__ __launch_bounds__(kBlock) void k_scan_blocks(const int* __restrict__ cnt, int* __restrict__ out,
+                                                        int64_t* __restrict__ bsum, int64_t n) {
+    __shared__ int64_t sh[kBlock];
+    const int tid = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kScanRows + 4 * tid;
+    int v[4];
+    int64_t t = 0;
+    for (int q = 0; q < 4; ++q) {
+        v[q] = (base + q < n) ? cnt[base + q] : 0;
+        t += v[q];
+    }
+    sh[tid] = t;
+    __syncthreads();
+    for (int o = 1; o < kBlock; o <<= 1) {  // inclusive scan of the thread totals
+        const int64_t x = (tid >= o) ? sh[tid - o] : 0;
+        __syncthreads();
+        sh[tid] += x;
+        __syncthreads();
+    }
+    int64_t run = sh[tid] - t;
+    for (int q = 0; q < 4; ++q) {
+        if (base + q < n) out[base + q] = (int)run;
+        run += v[q];
+    }
+    if (tid == kBlock - 1) bsum[blockIdx.x] = sh[tid];
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_totals(int64_t* __restrict__ bsum, int64_t nb, int64_t* __restrict__ total) {
+    __shared__ int64_t sh[kBlock];
+    const int tid = threadIdx.x;
+    int64_t off = 0;
+    for (int64_t c = 0; c < nb; c += kBlock) {
+        const int64_t x = (c + tid < nb) ? bsum[c + tid] : 0;
+        sh[tid] = x;
+        __syncthreads();
+        for (int o = 1; o < kBlock; o <<= 1) {
+            const int64_t y = (tid >= o) ? sh[tid - o] : 0;
+            __syncthreads();
+            sh[tid] += y;
+            __syncthreads();
+        }
+        if (c + tid < nb) bsum[c + tid] = off + sh[tid] - x;  // exclusive
+        off += sh[kBlock - 1];
+        __syncthreads();
+    }
+    if (tid == 0) *total = off;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_add(int* __restrict__ out, const int64_t* __restrict__ bsum,
+                                                     int64_t n, const int64_t* __restrict__ total) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) out[i] += (int)bsum[i / kScanRows];
+    if (i == n) out[n] = (int)*total;
+}
+
+// one wavefront per row: the row's entries (lane k: the hops between modes k and k + 1),
+// sorted by column in LDS, stored at row_ptr[r]
+__global__ __launch_bounds__(kBlock) void k_bose_fill(BoseArgs A, const int* __restrict__ row_ptr,
+                                                      int* __restrict__ col, double2* __restrict__ val) {
+    __shared__ int skey[kRowsPerBlock][128];
+    __shared__ double2 sval[kRowsPerBlock][128];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t r = (int64_t)blockIdx.x * kRowsPerBlock + w;
+    const bool live = r < A.dim;
+    const int64_t rr = live ? r : A.dim - 1;
+    int n, R;
+    bose_unrank(A, rr, lane, &n, &R);
+    const int n1 = __shfl_down(n, 1);  // occupation of mode lane + 1
+    // diagonal sum_k U_k n_k (n_k - 1), summed in mode order
+    const double term = (lane < A.K) ? (double)n * ((double)n - 1.0) * A.U[lane] : 0.0;
+    double diag = 0.0;
+    for (int k = 0; k < A.K; ++k) diag += __shfl(term, k);
+    for (int e = lane; e < A.slots; e += 64) {
+        skey[w][e] = INT_MAX;
+        sval[w][e] = make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    if (lane < A.K - 1) {
+        const double2 a = A.hop[lane];
+        // a_k b_k^+ b_{k+1} from the state with (n_k - 1, n_{k+1} + 1)
+        if (n > 0) {
+            const double sq = sqrt((double)(n1 + 1) * ((double)(n - 1) + 1.0));
+            skey[w][2 * lane] = (int)(rr + comp(A, R - n, A.K - lane - 1));
+            sval[w][2 * lane] = make_double2(a.x * sq, a.y * sq);
+        }
+        // conj(a_k) b_{k+1}^+ b_k from the state with (n_k + 1, n_{k+1} - 1)
+        if (n1 > 0) {
+            const double sq = sqrt((double)(n + 1) * ((double)(n1 - 1) + 1.0));
+            skey[w][2 * lane + 1] = (int)(rr - comp(A, R - n - 1, A.K - lane - 1));
+            sval[w][2 * lane + 1] = make_double2(a.x * sq, -a.y * sq);
+        }
+    }
+    if (lane == 0) {
+        skey[w][2 * (A.K - 1)] = (int)rr;
+        sval[w][2 * (A.K - 1)] = make_double2(diag, 0.0);
+    }
+    __syncthreads();
+    for (int k = 2; k <= A.slots; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = lane; i < A.slots; i += 64) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const int ki = skey[w][i], kl = skey[w][l];
+                    const bool up = (i & k) == 0;
+                    if ((ki > kl) == up) {
+                        skey[w][i] = kl;
+                        skey[w][l] = ki;
+                        const double2 t = sval[w][i];
+                        sval[w][i] = sval[w][l];
+                        sval[w][l] = t;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (!live) return;
+    const int start = row_ptr[rr], len = row_ptr[rr + 1] - start;
+    for (int e = lane; e < len; e += 64) {
+        col[start + e] = skey[w][e];
+        val[start + e] = sval[w][e];
+    }
+}
+
 }  // namespace
+
+static BoseArgs bose_args(const BoseChainDev& B) {
+    BoseArgs A;
+    A.K = B.K;
+    A.N = B.N;
+    A.slots = B.slots;
+    A.dim = B.dim;
+    A.bw = B.bw;
+    A.binom = B.binom;
+    A.U = B.U;
+    A.hop = B.hop;
+    return A;
+}
+
+hipError_t launch_bose_row_ptr(const BoseChainDev& B, int* row_ptr, int* cnt, int64_t* scratch, hipStream_t s) {
+    const BoseArgs A = bose_args(B);
+    const int64_t blocks = (B.dim + kRowsPerBlock - 1) / kRowsPerBlock;
+    k_bose_count<<<(unsigned)blocks, kBlock, 0, s>>>(A, cnt);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t nb = (B.dim + kScanRows - 1) / kScanRows;
+    k_scan_blocks<<<(unsigned)nb, kBlock, 0, s>>>(cnt, row_ptr, scratch, B.dim);
+    k_scan_totals<<<1, kBlock, 0, s>>>(scratch, nb, scratch + nb);
+    k_scan_add<<<(unsigned)((B.dim + 1 + kBlock - 1) / kBlock), kBlock, 0, s>>>(row_ptr, scratch, B.dim, scratch + nb);
+    return hipGetLastError();
+}
+
+hipError_t launch_bose_fill(const BoseChainDev& B, const int* row_ptr, int* col, double2* val, hipStream_t s) {
+    const BoseArgs A = bose_args(B);
+    const int64_t blocks = (B.dim + kRowsPerBlock - 1) / kRowsPerBlock;
+    k_bose_fill<<<(unsigned)blocks, kBlock, 0, s>>>(A, row_ptr, col, val);
+    return hipGetLastError();
+}
 
 hipError_t launch_memory_burden(const MemoryBurdenDev& M, int* row_ptr, int* col, double* val, hipStream_t s) {
     ModelArgs A;

@@ -278,6 +278,26 @@ struct MemoryBurdenDev {
 };
 hipError_t launch_memory_burden(const MemoryBurdenDev& M, int* row_ptr, int* col, double* val, hipStream_t s);
 
+// Device construction of the Bose chain (models.hip): K modes, N bosons, on-site interaction and
+// nearest-neighbour hopping; tables prepared by te_hamiltonian_create_bose_chain.
+struct BoseChainDev {
+    int K, N;
+    int slots;             // power of two >= 2K - 1, <= 128
+    int64_t dim;           // <= kMaxModelRows
+    int bw;                // row stride of binom
+    const int64_t* binom;  // [(N + K + 1) * bw] binomials C(a, b), b <= K
+    const double* U;       // [K]
+    const double2* hop;    // [K - 1]
+};
+// Row counts and their exclusive scan: row_ptr[dim + 1]; cnt: dim ints; scratch: dim / 1024 + 2
+// int64, whose entry [ceil(dim / 1024)] receives the number of entries.
+hipError_t launch_bose_row_ptr(const BoseChainDev& B, int* row_ptr, int* cnt, int64_t* scratch, hipStream_t s);
+// Columns (ascending per row) and values of every row, into arrays of row_ptr[dim] entries.
+hipError_t launch_bose_fill(const BoseChainDev& B, const int* row_ptr, int* col, double2* val, hipStream_t s);
+// Rows of a matrix built on the device: one wavefront per row, 4 rows per 256-thread workgroup,
+// so the grid's thread count stays below 2^32.
+constexpr int64_t kMaxModelRows = (int64_t)1 << 26;
+
 // batched launchers: items are (group or job, tile) pairs, one workgroup each
 hipError_t launch_gproject(int g, int u, int rpt, int nv_class, const JobView* jobs, const GroupView* groups,
                            const int2* items, int n_items, int j, hipStream_t s);

@@ -153,6 +153,8 @@ _SIGS = {
     "te_hamiltonian_copy_csr": (_I, [_P, _P, _P, _P, ctypes.c_uint32, _P]),
     "te_memory_burden_defaults": (None, [ctypes.c_void_p]),
     "te_hamiltonian_create_memory_burden": (_I, [ctypes.POINTER(_P), ctypes.c_void_p, ctypes.POINTER(_I64), _P]),
+    "te_hamiltonian_create_bose_chain": (_I, [ctypes.POINTER(_P), ctypes.c_int32, ctypes.c_int32, _P, _P,
+                                              ctypes.c_uint32, _P]),
     "te_workspace_bytes": (ctypes.c_size_t, [_I64, _I]),
     "te_set_allocator": (_I, [_P, _P, _P]),
     "te_evolve": (_I, [_P, _P, _P, _D, _D, _I, ctypes.POINTER(te_options), ctypes.POINTER(te_result), _P]),
@@ -313,6 +315,21 @@ def te_hamiltonian_create_memory_burden(model=None, stream=None, **overrides):
     _check(_lib.te_hamiltonian_create_memory_burden(ctypes.byref(h), ctypes.byref(p), ctypes.byref(idx),
                                                     _stream(stream)))
     return Hamiltonian(h), idx.value
+
+
+def te_hamiltonian_create_bose_chain(U, hop, N: int, store_complex=False, stream=None) -> Hamiltonian:
+    """Open Bose chain of len(U) modes and N bosons built on the device: hop[k] couples modes k
+    and k + 1 (len(hop) = len(U) - 1), U[k] n_k (n_k - 1) on site."""
+    u = np.ascontiguousarray(U, dtype=np.float64)
+    a = np.ascontiguousarray(hop, dtype=np.complex128)
+    if u.ndim != 1 or a.shape != (max(u.size - 1, 0),):
+        raise ValueError("need len(hop) == len(U) - 1")
+    h = _P()
+    flags = TE_STORE_COMPLEX if store_complex else 0
+    _check(_lib.te_hamiltonian_create_bose_chain(ctypes.byref(h), int(u.size), int(N), ctypes.c_void_p(u.ctypes.data),
+                                                 ctypes.c_void_p(a.ctypes.data) if a.size else None, flags,
+                                                 _stream(stream)))
+    return Hamiltonian(h)
 
 
 def te_hamiltonian_copy_csr(H: Hamiltonian, stream=None):

@@ -120,13 +120,18 @@ def hopping_triplets(basis, index, src_mode, dst_mode, amp, caps=None):
     return target, source, value
 
 
-def bosonic_chain(K: int, N: int, seed: int, with_v0: bool = True):
-    """Return (CSR, v0) for the complex-hopping Bose chain with on-site interaction."""
-    rng = np.random.default_rng(seed)
+def bose_chain_params(rng: np.random.Generator, K: int):
+    """(U, a) of the chain, drawn in the documented order."""
     r = rng.uniform(0.5, 1.5, K - 1)
     theta = rng.uniform(0.0, 2.0 * np.pi, K - 1)
     U = rng.uniform(0.0, 2.0, K)
-    a = r * np.exp(1j * theta)
+    return U, r * np.exp(1j * theta)
+
+
+def bosonic_chain(K: int, N: int, seed: int, with_v0: bool = True):
+    """Return (CSR, v0) for the complex-hopping Bose chain with on-site interaction."""
+    rng = np.random.default_rng(seed)
+    U, a = bose_chain_params(rng, K)
 
     basis = fock_basis(K, N)
     d = basis.shape[0]
