@@ -149,7 +149,11 @@ def bench_batch(te, torch, dev, n_instances, m, profile):
         for vi, v in enumerate(vs):
             out, res = te.te_evolve(h, v, t, tol, m)
             seq_done.append(time.perf_counter() - s0)
-            worst = max(worst, float((out - outs[gi][vi]).norm()) / max(res.err_bound + results[k][0].err_bound, 1e-300))
+            # two valid results differ by at most the two bounds plus the rounding of the two
+            # computations (the paper's roundoff estimate), since the shapes differ
+            allowed = (res.err_bound + results[k][0].err_bound + res.num_err_estimate
+                       + results[k][0].num_err_estimate)
+            worst = max(worst, float((out - outs[gi][vi]).norm()) / max(allowed, 1e-300))
             k += 1
     seq_s = time.perf_counter() - s0
     log(f"[bench] one at a time: {seq_s:.2f} s, {n_jobs / seq_s:.1f} states/s")
@@ -167,7 +171,7 @@ def bench_batch(te, torch, dev, n_instances, m, profile):
         "pool_peak_gb": stats.pool_peak / 1e9,
         "shape": {"lanes_per_row": stats.tuning.lanes_per_row, "nnz_per_lane": stats.tuning.nnz_per_lane,
                   "update_rows_per_thread": stats.tuning.update_rows_per_thread},
-        "max_diff_over_bounds_vs_one_at_a_time": worst,
+        "max_diff_over_bounds_and_roundoff_vs_one_at_a_time": worst,
     }
     if prof:
         rec["profile"] = {"kernel_gbs": kernel_rates(prof),
@@ -249,7 +253,7 @@ def bench_serving(te, torch, dev, n_requests, qps, m, budget_gb, sweep=(), sweep
         out, rr = te.te_evolve(hs[r.hamiltonian_key()], v, r.t, r.tol, m)
         torch.cuda.synchronize()
         service.append(time.perf_counter() - s0)
-        ref.append((out.clone(), rr.err_bound))
+        ref.append((out.clone(), rr.err_bound + rr.num_err_estimate))
         if (i + 1) % 25 == 0:
             log(f"[bench] one at a time: {i + 1} requests")
 
@@ -267,7 +271,8 @@ def bench_serving(te, torch, dev, n_requests, qps, m, budget_gb, sweep=(), sweep
         first = min(i.submitted for i, _ in infos)
         last = max(i.finished for i, _ in infos)
         lat = [i.finished - i.submitted for i, _ in infos]
-        worst = max(float((o - ref[k][0]).norm()) / max(ref[k][1] + infos[k][1].err_bound, 1e-300)
+        worst = max(float((o - ref[k][0]).norm())
+                    / max(ref[k][1] + infos[k][1].err_bound + infos[k][1].num_err_estimate, 1e-300)
                     for k, o in enumerate(outs))
         f_rate, f_lat = fifo(arrivals, n)
         rec = {"requests": n, "qps": q, "states_per_s": n / (last - first), "seconds": last - first,
@@ -275,7 +280,7 @@ def bench_serving(te, torch, dev, n_requests, qps, m, budget_gb, sweep=(), sweep
                "one_at_a_time_fifo": {"states_per_s": f_rate, "latency_ms": latency_summary(f_lat)},
                "rounds": st.rounds, "plans": st.plans, "pool_peak_gb": st.pool_peak / 1e9,
                "failed": sum(1 for i, _ in infos if i.state != te.TE_JOB_DONE),
-               "max_diff_over_bounds_vs_one_at_a_time": worst}
+               "max_diff_over_bounds_and_roundoff_vs_one_at_a_time": worst}
         log(f"[bench] {label}: {rec['states_per_s']:.2f} states/s, p50 {rec['latency_ms']['p50'] / 1e3:.3f} s, "
             f"p99 {rec['latency_ms']['p99'] / 1e3:.3f} s | one at a time {f_rate:.2f} states/s, "
             f"p50 {rec['one_at_a_time_fifo']['latency_ms']['p50'] / 1e3:.3f} s, "
@@ -344,7 +349,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="xxz_L20")
     ap.add_argument("--cpu-restarts", type=int, default=2, help="restarts of the CPU oracle sample (0: skip)")
-    ap.add_argument("--shape", default="8,2,4,2,1",
+    ap.add_argument("--shape", default="1,8,4,2,1",
                     help="projection kernel shape lanes,nnz,rows,update_rows,split for the single solve "
                          "(default: the shape te_autotune selects for this matrix on MI355X), or 'auto'")
     ap.add_argument("--three-term", type=int, default=1, help="also time the three-term mode (0: skip)")

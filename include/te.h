@@ -62,6 +62,7 @@ enum {
 #define TE_PTR_DEVICE 1u      /* row_ptr/col_idx/values are device pointers (else host) */
 #define TE_CHECK_HERMITIAN 2u /* verify H == H^H on the device (needs sorted columns) */
 #define TE_STORE_COMPLEX 4u   /* keep 16-byte complex entries even when all are real */
+#define TE_STORE_CSR 8u       /* keep column indices and values per entry (no packing) */
 
 #define TE_MAX_KRYLOV 64 /* largest Krylov dimension m: a row of the small eigenproblem is held
                             by one 64-lane wavefront */
@@ -147,13 +148,31 @@ const char* te_last_error(void);
  * models of the paper's examples) the device copy keeps only the real parts, 8 bytes per
  * entry instead of 16: the sparse products then stream 12 instead of 20 bytes per entry and
  * give the same values (a zero imaginary part adds exact zeros).  TE_STORE_COMPLEX keeps
- * the complex copy regardless. */
+ * the complex copy regardless.
+ * Packing: the Hamiltonians of lattice models are sums of a few local terms, so their entries
+ * off the diagonal take few distinct (column - row, value) pairs (the XXZ ring: 2 per bond).
+ * When there are at most 65535 such pairs, every diagonal entry is real (imaginary part +0)
+ * and no row stores its diagonal twice, the device copy keeps per entry only a 1-byte (at most
+ * 255 pairs) or 2-byte code into a table of the pairs, plus the real diagonal per row, and
+ * drops the column indices and values: a sparse product then streams 1 or 2 bytes per entry
+ * and 8 per row instead of 20 (or 12) per entry, and gives bitwise the values of the CSR it
+ * was packed from (same entries, same order).  The test is one host pass over the entries
+ * (read back from the device in chunks).  TE_STORE_CSR keeps the CSR regardless. */
 te_status te_hamiltonian_create(te_hamiltonian* out, int64_t dim, int64_t nnz,
                                 const int32_t* row_ptr, const int32_t* col_idx,
                                 const te_c128* values, uint32_t flags, void* stream);
 
 /* *real_values = 1 when the handle stores real entries (see te_hamiltonian_create), else 0. */
 te_status te_hamiltonian_real_values(te_hamiltonian h, int32_t* real_values);
+
+/* Storage of the handle's entries (see te_hamiltonian_create). */
+enum {
+    TE_STORAGE_COMPLEX = 0,   /* column + complex value per entry (20 bytes) */
+    TE_STORAGE_REAL = 1,      /* column + real value per entry (12 bytes) */
+    TE_STORAGE_PACKED8 = 2,   /* 1-byte code per entry + real diagonal per row */
+    TE_STORAGE_PACKED16 = 3   /* 2-byte code per entry + real diagonal per row */
+};
+te_status te_hamiltonian_storage(te_hamiltonian h, int32_t* kind);
 
 /* Copies the handle's CSR out: row_ptr[dim+1], col_idx[nnz], values[nnz] (complex; real
  * entries are returned with zero imaginary parts).  Device pointers with TE_PTR_DEVICE, else
@@ -280,10 +299,11 @@ te_status te_last_profile(te_hamiltonian h, te_profile* out);
  * product fused with the projections) is timed on the handle's own matrix for every supported
  * shape and the fastest is kept; te_evolve tunes a handle on first use unless the environment
  * sets TE_AUTOTUNE=0.  If TE_TUNE_CACHE names a file, results are read from / appended to it
- * (one line per "gfx950 dim nnz m" key). */
+ * (one line per "gfx950/<storage> dim nnz m" key, storage as named by TE_STORAGE_*). */
 typedef struct {
-    int32_t lanes_per_row;          /* lanes sharing one row of the sparse product: 4 or 8 */
-    int32_t nnz_per_lane;           /* nonzeros per lane in flight: 1 or 4 (4 lanes), 2 (8 lanes) */
+    int32_t lanes_per_row;          /* lanes sharing one row of the sparse product: 1, 2, 4 or 8 */
+    int32_t nnz_per_lane;           /* nonzeros per lane in flight: 8 (1 or 2 lanes), 1 or 4
+                                       (4 lanes), 2 (8 lanes) */
     int32_t rows_per_thread;        /* projection kernel: 1, 2 or 4 (4: batches of 4 columns) */
     int32_t update_rows_per_thread; /* update and recombination kernels: 1 or 2 */
     int32_t split_projection;       /* 0: sparse product fused with the projections in one kernel;

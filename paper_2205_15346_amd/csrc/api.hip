@@ -132,6 +132,10 @@ te_hamiltonian_s::~te_hamiltonian_s() {
     dev_free(col);
     dev_free(val);
     dev_free(rval);
+    dev_free(code);
+    dev_free(toff);
+    dev_free(tval);
+    dev_free(diag);
 }
 
 namespace {
@@ -239,7 +243,7 @@ hipError_t accumulate_profile(te_hamiltonian h, Workspace* w, std::vector<hipEve
         p->seconds[TE_KERNEL_PROJECT] += t;
         // CSR (values, columns, row pointers), columns i_lo..j of V, y written
         const int cols = (three_term && j >= 1) ? 2 : j + 1;
-        p->bytes[TE_KERNEL_PROJECT] += csr_entry_bytes(h->csr) * nnz + 4.0 * (d + 1) + 16.0 * d * (cols + 1);
+        p->bytes[TE_KERNEL_PROJECT] += csr_entries_bytes(h->csr) + 4.0 * (d + 1) + 16.0 * d * (cols + 1);
         e = span(3 * j + 1, 3 * j + 2, &t);
         if (e != hipSuccess) return e;
         p->launches[TE_KERNEL_FOLD] += 1;
@@ -301,8 +305,12 @@ te_status retile(te_hamiltonian h, Workspace* w, const Tiling& t) {
     return ensure_graph(h, w);
 }
 
+// "gfx950/<storage> dim nnz m": the best shape depends on how the entries are stored
 std::string tune_key(te_hamiltonian h, int m) {
-    return "gfx950 " + std::to_string(h->csr.dim) + " " + std::to_string(h->csr.nnz) + " " + std::to_string(m);
+    const Csr& c = h->csr;
+    const char* storage = c.pk.c8 ? "packed8" : c.pk.c16 ? "packed16" : c.rval ? "real" : "complex";
+    return std::string("gfx950/") + storage + " " + std::to_string(c.dim) + " " + std::to_string(c.nnz) + " " +
+           std::to_string(m);
 }
 
 bool tune_cache_lookup(const std::string& key, te_tuning* t) {
@@ -360,7 +368,7 @@ te_status run_autotune(te_hamiltonian h, Workspace* w, hipStream_t s) {
     TE_HIP(hipEventCreate(&e0));
     TE_HIP(hipEventCreate(&e1));
     const int rpt_u = default_tiling(w->dim).rpt_u;
-    const int shapes[3][2] = {{4, 1}, {4, 4}, {8, 2}};
+    const int shapes[6][2] = {{4, 1}, {4, 4}, {8, 2}, {2, 8}, {1, 8}, {1, 16}};
     double best_us = 1e30;
     hipError_t err = hipSuccess;
     for (int sp = 0; sp <= 1 && err == hipSuccess; ++sp)
@@ -533,13 +541,165 @@ static te_status keep_real_entries(te_hamiltonian h, hipStream_t s) {
     return TE_OK;
 }
 
+// Packing of the stored entries (te::Packed).  One host pass over the entries, read back from
+// the device in chunks, collects the distinct (column - row, value) pairs off the diagonal in
+// an open-addressing table (values compared bit for bit).  The matrix stays in CSR form
+// (*packed = false) when there are more than 65535 pairs, a diagonal entry has an imaginary
+// part other than +0, or a row stores its diagonal twice.
+namespace {
+
+struct PairKey {
+    int32_t off;
+    uint64_t re, im;
+};
+
+inline uint64_t mix64(uint64_t x) {  // the splitmix64 finaliser
+    x ^= x >> 30;
+    x *= 0xbf58476d1ce4e5b9ull;
+    x ^= x >> 27;
+    x *= 0x94d049bb133111ebull;
+    return x ^ (x >> 31);
+}
+
+constexpr int kMaxPairs = 65535;
+constexpr int kPairSlots = 1 << 17;  // load factor <= 1/2
+constexpr int64_t kPackChunk = (int64_t)1 << 22;
+constexpr size_t kCodePad = 64;  // >= the largest batch of codes + 4 bytes
+
+}  // namespace
+
+static te_status try_pack(te_hamiltonian h, hipStream_t s, bool* packed) {
+    *packed = false;
+    const int dim = h->csr.dim;
+    const int64_t nnz = h->csr.nnz;
+    std::vector<int> rp;
+    std::vector<uint16_t> code;
+    std::vector<double> diag;
+    std::vector<int> cbuf;
+    std::vector<double2> vbuf;
+    std::vector<int32_t> slot(kPairSlots, -1);
+    std::vector<PairKey> keys(kPairSlots);
+    std::vector<int> toff;
+    std::vector<double2> tval;
+    try {
+        rp.resize((size_t)dim + 1);
+        code.resize((size_t)nnz);
+        diag.assign((size_t)dim, 0.0);
+        cbuf.resize((size_t)std::min(nnz, kPackChunk));
+        vbuf.resize((size_t)std::min(nnz, kPackChunk));
+    } catch (...) {
+        return TE_OK;  // no host memory for the pass: keep CSR
+    }
+    constexpr uint16_t kDiag = 0xFFFF;  // placeholder until the diagonal's code is known
+    TE_HIP(hipMemcpyAsync(rp.data(), h->csr.row_ptr, ((size_t)dim + 1) * sizeof(int), hipMemcpyDeviceToHost, s));
+    TE_HIP(hipStreamSynchronize(s));
+    int r = 0, diag_row = -1;
+    for (int64_t k0 = 0; k0 < nnz; k0 += kPackChunk) {
+        const int64_t n = std::min(kPackChunk, nnz - k0);
+        TE_HIP(hipMemcpyAsync(cbuf.data(), h->csr.col + k0, (size_t)n * sizeof(int), hipMemcpyDeviceToHost, s));
+        TE_HIP(hipMemcpyAsync(vbuf.data(), h->csr.val + k0, (size_t)n * sizeof(double2), hipMemcpyDeviceToHost, s));
+        TE_HIP(hipStreamSynchronize(s));
+        for (int64_t i = 0; i < n; ++i) {
+            const int64_t k = k0 + i;
+            while (rp[(size_t)r + 1] <= k) ++r;
+            const int c = cbuf[(size_t)i];
+            const double2 v = vbuf[(size_t)i];
+            uint64_t re, im;
+            std::memcpy(&re, &v.x, 8);
+            std::memcpy(&im, &v.y, 8);
+            if (c == r) {
+                if (im != 0 || diag_row == r) return TE_OK;
+                diag_row = r;
+                diag[(size_t)r] = v.x;
+                code[(size_t)k] = kDiag;
+                continue;
+            }
+            const int32_t off = c - r;
+            uint32_t q = (uint32_t)mix64(((uint64_t)(uint32_t)off << 32) ^ mix64(re) ^ (mix64(im) * 3u)) & (kPairSlots - 1);
+            while (slot[q] >= 0 && !(keys[q].off == off && keys[q].re == re && keys[q].im == im))
+                q = (q + 1) & (kPairSlots - 1);
+            if (slot[q] < 0) {
+                if ((int)toff.size() == kMaxPairs) return TE_OK;
+                slot[q] = (int32_t)toff.size();
+                keys[q] = PairKey{off, re, im};
+                toff.push_back(off);
+                tval.push_back(v);
+            }
+            code[(size_t)k] = (uint16_t)slot[q];
+        }
+    }
+    const int dcode = (int)toff.size();  // the diagonal's code follows the pairs
+    toff.push_back(0);
+    tval.push_back(make_double2(0.0, 0.0));
+    const bool narrow = dcode <= 255;
+    const size_t cbytes = (size_t)nnz * (narrow ? 1 : 2);
+    // padded (zero bytes): a batch of 1-byte codes is read as whole dwords and may run past the end
+    void* d_code = dev_alloc(cbytes + kCodePad);
+    int* d_toff = (int*)dev_alloc(toff.size() * sizeof(int));
+    double2* d_tval = (double2*)dev_alloc(tval.size() * sizeof(double2));
+    double* d_diag = (double*)dev_alloc((size_t)dim * sizeof(double));
+    if (!d_code || !d_toff || !d_tval || !d_diag) {
+        dev_free(d_code);
+        dev_free(d_toff);
+        dev_free(d_tval);
+        dev_free(d_diag);
+        return TE_OK;  // no device memory for the packed copy: keep CSR
+    }
+    std::vector<uint8_t> code8;
+    if (narrow) {
+        code8.resize((size_t)nnz);
+        for (int64_t k = 0; k < nnz; ++k) code8[(size_t)k] = code[(size_t)k] == kDiag ? (uint8_t)dcode : (uint8_t)code[(size_t)k];
+    } else {
+        for (int64_t k = 0; k < nnz; ++k)
+            if (code[(size_t)k] == kDiag) code[(size_t)k] = (uint16_t)dcode;
+    }
+    te_status rc = TE_OK;
+    hipError_t e = hipMemsetAsync((char*)d_code + cbytes, 0, kCodePad, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_code, narrow ? (const void*)code8.data() : (const void*)code.data(), cbytes,
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_toff, toff.data(), toff.size() * sizeof(int), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_tval, tval.data(), tval.size() * sizeof(double2), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_diag, diag.data(), (size_t)dim * sizeof(double), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        rc = fail(TE_ERR_DEVICE, std::string("packing the entries: ") + hipGetErrorString(e));
+        dev_free(d_code);
+        dev_free(d_toff);
+        dev_free(d_tval);
+        dev_free(d_diag);
+        return rc;
+    }
+    h->code = d_code;
+    h->toff = d_toff;
+    h->tval = d_tval;
+    h->diag = d_diag;
+    Packed pk;
+    if (narrow) pk.c8 = (const uint8_t*)d_code;
+    else pk.c16 = (const uint16_t*)d_code;
+    pk.toff = d_toff;
+    pk.tval = d_tval;
+    pk.diag = d_diag;
+    pk.dcode = dcode;
+    h->csr.pk = pk;
+    dev_free(h->col);
+    dev_free(h->val);
+    h->col = nullptr;
+    h->val = nullptr;
+    h->csr.col = nullptr;
+    h->csr.val = nullptr;
+    *packed = true;
+    return TE_OK;
+}
+
 te_status te_hamiltonian_create(te_hamiltonian* out, int64_t dim, int64_t nnz, const int32_t* row_ptr,
                                 const int32_t* col_idx, const te_c128* values, uint32_t flags, void* stream) {
     if (!out || !row_ptr || !col_idx || !values) return fail(TE_ERR_INVALID_ARG, "null pointer");
     *out = nullptr;
     if (dim < 1 || dim >= ((int64_t)1 << 31) - 1) return fail(TE_ERR_INVALID_ARG, "dim out of range");
     if (nnz < 1 || nnz >= ((int64_t)1 << 31)) return fail(TE_ERR_INVALID_CSR, "nnz out of range (1..2^31-1)");
-    if (flags & ~(TE_PTR_DEVICE | TE_CHECK_HERMITIAN | TE_STORE_COMPLEX)) return fail(TE_ERR_INVALID_ARG, "unknown flags");
+    if (flags & ~(TE_PTR_DEVICE | TE_CHECK_HERMITIAN | TE_STORE_COMPLEX | TE_STORE_CSR))
+        return fail(TE_ERR_INVALID_ARG, "unknown flags");
     hipStream_t s = (hipStream_t)stream;
     auto* h = new (std::nothrow) te_hamiltonian_s();
     if (!h) return fail(TE_ERR_OUT_OF_MEMORY, "host allocation failed");
@@ -575,7 +735,9 @@ te_status te_hamiltonian_create(te_hamiltonian* out, int64_t dim, int64_t nnz, c
     if (rc == TE_OK) rc = validate_handle(h, (flags & TE_CHECK_HERMITIAN) ? 1 : 0, err, rowsum, &herr, s);
     dev_free(rowsum);
     dev_free(err);
-    if (rc == TE_OK && !(herr & 32) && !(flags & TE_STORE_COMPLEX)) rc = keep_real_entries(h, s);
+    bool packed = false;
+    if (rc == TE_OK && !(flags & TE_STORE_CSR)) rc = try_pack(h, s, &packed);
+    if (rc == TE_OK && !packed && !(herr & 32) && !(flags & TE_STORE_COMPLEX)) rc = keep_real_entries(h, s);
     if (rc != TE_OK) {
         delete h;
         return rc;
@@ -597,6 +759,14 @@ te_status te_hamiltonian_real_values(te_hamiltonian h, int32_t* real_values) {
     return TE_OK;
 }
 
+te_status te_hamiltonian_storage(te_hamiltonian h, int32_t* kind) {
+    if (!h || !kind) return fail(TE_ERR_INVALID_ARG, "null pointer");
+    *kind = h->csr.pk.c8 ? TE_STORAGE_PACKED8 : h->csr.pk.c16 ? TE_STORAGE_PACKED16
+                                              : h->csr.rval   ? TE_STORAGE_REAL
+                                                              : TE_STORAGE_COMPLEX;
+    return TE_OK;
+}
+
 te_status te_hamiltonian_copy_csr(te_hamiltonian h, int32_t* row_ptr, int32_t* col_idx, te_c128* values,
                                   uint32_t flags, void* stream) {
     if (!h) return fail(TE_ERR_INVALID_ARG, "null handle");
@@ -605,6 +775,21 @@ te_status te_hamiltonian_copy_csr(te_hamiltonian h, int32_t* row_ptr, int32_t* c
     const bool dev = (flags & TE_PTR_DEVICE) != 0;
     const hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     const int64_t dim = h->csr.dim, nnz = h->csr.nnz;
+    if (is_packed(h->csr.pk)) {  // expand into device scratch, then copy out
+        int* c = (int*)dev_alloc((size_t)nnz * sizeof(int));
+        double2* v = (double2*)dev_alloc((size_t)nnz * sizeof(double2));
+        hipError_t e = (c && v) ? launch_expand_packed(h->csr.row_ptr, h->csr.pk, h->csr.dim, c, v, s) : hipErrorOutOfMemory;
+        if (e == hipSuccess && row_ptr) e = hipMemcpyAsync(row_ptr, h->csr.row_ptr, (dim + 1) * sizeof(int), kind, s);
+        if (e == hipSuccess && col_idx) e = hipMemcpyAsync(col_idx, c, nnz * sizeof(int), kind, s);
+        if (e == hipSuccess && values) e = hipMemcpyAsync(values, v, nnz * sizeof(double2), kind, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        dev_free(c);
+        dev_free(v);
+        if (e != hipSuccess)
+            return fail(e == hipErrorOutOfMemory ? TE_ERR_OUT_OF_MEMORY : TE_ERR_DEVICE,
+                        std::string("expanding the packed entries: ") + hipGetErrorString(e));
+        return TE_OK;
+    }
     if (row_ptr) TE_HIP(hipMemcpyAsync(row_ptr, h->csr.row_ptr, (dim + 1) * sizeof(int), kind, s));
     if (col_idx) TE_HIP(hipMemcpyAsync(col_idx, h->csr.col, nnz * sizeof(int), kind, s));
     if (values) {

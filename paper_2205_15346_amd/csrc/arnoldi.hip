@@ -29,7 +29,8 @@ namespace te {
 int max_tiles(int dim) { return (dim + kBlock - 1) / kBlock; }
 
 bool tiling_supported(int rpt_p, int g, int u, int rpt_u, int split) {
-    const bool shape = (g == 4 && (u == 1 || u == 4)) || (g == 8 && u == 2);
+    const bool shape = (g == 4 && (u == 1 || u == 4)) || (g == 8 && u == 2) || (g == 2 && u == 8) ||
+                       (g == 1 && (u == 8 || u == 16));
     return shape && (rpt_p == 1 || rpt_p == 2 || rpt_p == 4) && (rpt_u == 1 || rpt_u == 2) && (split == 0 || split == 1);
 }
 
@@ -189,17 +190,69 @@ __device__ __forceinline__ double2 entry_zero<double2>() { return make_double2(0
 template <>
 __device__ __forceinline__ double entry_zero<double>() { return 0.0; }
 
-// y = H V[:, j] (raw) on rows [r0, r1): G lanes per row stream the CSR, each with U nonzeros
-// in flight; results to y and, if ytile is given, to LDS.
-template <int G, int U, typename VT>
-__device__ __forceinline__ void tile_spmv_t(const int* __restrict__ rp, const int* __restrict__ ci,
-                                            const VT* __restrict__ val, const double2* __restrict__ x,
+// Sources of a row's stored entries: (column, value) of entry k.  CSR keeps both per entry;
+// packed entries keep a code into a table of (column offset, value) pairs and, for the
+// diagonal, the row's real diagonal (the sum runs over the same entries in the same order, so
+// the products are bitwise those of the CSR they were packed from).
+template <typename VT>
+struct CsrSrc {
+    const int* __restrict__ ci;
+    const VT* __restrict__ val;
+    using V = VT;
+    __device__ __forceinline__ CsrSrc row(int) const { return *this; }
+    __device__ __forceinline__ void load(int k, int& c, VT& v) const {
+        c = ci[k];
+        v = val[k];
+    }
+};
+
+template <typename CT>
+struct PackSrc {
+    const CT* __restrict__ code;
+    const int* __restrict__ toff;
+    const double2* __restrict__ tval;
+    const double* __restrict__ diag;
+    int dcode;
+    int r = 0;
+    double dg = 0.0;
+    using V = double2;
+    __device__ __forceinline__ PackSrc row(int rr) const {
+        PackSrc p = *this;
+        p.r = rr;
+        p.dg = diag[rr];
+        return p;
+    }
+    __device__ __forceinline__ void load(int k, int& c, double2& v) const {
+        const int q = code[k];
+        c = r + toff[q];
+        const double2 t = tval[q];
+        v = (q == dcode) ? make_double2(dg, 0.0) : t;
+    }
+};
+
+// Calls f with the source of the matrix's storage kind.
+template <typename F>
+__device__ __forceinline__ void with_entries(const int* ci, const double2* val, const double* rval, const Packed& pk,
+                                             F&& f) {
+    if (pk.c8) f(PackSrc<uint8_t>{pk.c8, pk.toff, pk.tval, pk.diag, pk.dcode});
+    else if (pk.c16) f(PackSrc<uint16_t>{pk.c16, pk.toff, pk.tval, pk.diag, pk.dcode});
+    else if (rval) f(CsrSrc<double>{ci, rval});
+    else f(CsrSrc<double2>{ci, val});
+}
+
+// y = H V[:, j] (raw) on rows [r0, r1): G lanes per row stream the stored entries, each with U
+// entries in flight; results to y and, if ytile is given, to LDS.
+template <int G, int U, typename Src>
+__device__ __forceinline__ void tile_spmv_t(const int* __restrict__ rp, const Src& src,
+                                            const double2* __restrict__ x,
                                             int r0, int r1, double2* __restrict__ y, double2* ytile) {
+    using VT = typename Src::V;
     const int tid = threadIdx.x;
     const int lg = tid % G, grp = tid / G;
     for (int r = r0 + grp; r < r1; r += kBlock / G) {
         double2 acc = make_double2(0.0, 0.0);
         const int kb = rp[r], ke = rp[r + 1];
+        const Src rs = src.row(r);
         for (int k0 = kb + lg; k0 < ke; k0 += G * U) {
             VT vv[U];
             int cc[U];
@@ -207,8 +260,7 @@ __device__ __forceinline__ void tile_spmv_t(const int* __restrict__ rp, const in
             for (int q = 0; q < U; ++q) {
                 const int k = k0 + q * G;
                 if (k < ke) {
-                    vv[q] = val[k];
-                    cc[q] = ci[k];
+                    rs.load(k, cc[q], vv[q]);
                 } else {
                     vv[q] = entry_zero<VT>();
                     cc[q] = -1;
@@ -230,13 +282,78 @@ __device__ __forceinline__ void tile_spmv_t(const int* __restrict__ rp, const in
     }
 }
 
+// One row per thread, 1-byte codes.  The U * H codes of a batch come from U * H / 4 + 1 aligned
+// dword loads (the code array is padded so that the last batch's over-read stays inside it),
+// byte-aligned with v_alignbyte; their gathers follow in H groups of U.  A row of up to U * H
+// entries thus costs one round trip for its codes and the gathers behind it.
+template <int U, int H>
+__device__ __forceinline__ void tile_spmv_p8_rows(const int* __restrict__ rp, const uint8_t* __restrict__ code,
+                                                  const int* toff, const double2* tval,
+                                                  const double* __restrict__ diag, int dcode,
+                                                  const double2* __restrict__ x, int r0, int r1,
+                                                  double2* __restrict__ y, double2* ytile) {
+    constexpr int CB = U * H;
+    static_assert(CB % 4 == 0, "batches of whole dwords");
+    const uint32_t* __restrict__ words = reinterpret_cast<const uint32_t*>(code);
+    for (int r = r0 + (int)threadIdx.x; r < r1; r += kBlock) {
+        double2 acc = make_double2(0.0, 0.0);
+        const int kb = rp[r], ke = rp[r + 1];
+        const double dg = diag[r];
+        for (int k0 = kb; k0 < ke; k0 += CB) {
+            uint32_t w[CB / 4 + 1];
+#pragma unroll
+            for (int i = 0; i <= CB / 4; ++i) w[i] = words[(k0 >> 2) + i];
+            uint32_t b[CB / 4];
+#pragma unroll
+            for (int i = 0; i < CB / 4; ++i) b[i] = __builtin_amdgcn_alignbyte(w[i + 1], w[i], (uint32_t)(k0 & 3));
+#pragma unroll
+            for (int h = 0; h < H; ++h) {
+                double2 vv[U];
+                int cc[U];
+#pragma unroll
+                for (int q = 0; q < U; ++q) {
+                    const int e = h * U + q;
+                    const int c8 = (int)((b[e >> 2] >> (8 * (e & 3))) & 0xffu);
+                    if (k0 + e < ke) {
+                        cc[q] = r + toff[c8];
+                        const double2 t = tval[c8];
+                        vv[q] = (c8 == dcode) ? make_double2(dg, 0.0) : t;
+                    } else {
+                        cc[q] = -1;
+                        vv[q] = make_double2(0.0, 0.0);
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < U; ++q)
+                    if (cc[q] >= 0) acc = entry_fma(vv[q], x[cc[q]], acc);
+            }
+        }
+        y[r] = acc;
+        if (ytile) ytile[r - r0] = acc;
+    }
+}
+
+// Whole block.  A table of 1-byte codes (at most 256 pairs) is staged in LDS first.
 template <int G, int U>
 __device__ __forceinline__ void tile_spmv(const int* __restrict__ rp, const int* __restrict__ ci,
                                           const double2* __restrict__ val, const double* __restrict__ rval,
-                                          const double2* __restrict__ x, int r0, int r1, double2* __restrict__ y,
-                                          double2* ytile) {
-    if (rval) tile_spmv_t<G, U, double>(rp, ci, rval, x, r0, r1, y, ytile);
-    else tile_spmv_t<G, U, double2>(rp, ci, val, x, r0, r1, y, ytile);
+                                          const Packed& pk, const double2* __restrict__ x, int r0, int r1,
+                                          double2* __restrict__ y, double2* ytile) {
+    if (pk.c8) {
+        __shared__ int s_toff[256];
+        __shared__ double2 s_tval[256];
+        for (int i = threadIdx.x; i <= pk.dcode; i += kBlock) {
+            s_toff[i] = pk.toff[i];
+            s_tval[i] = pk.tval[i];
+        }
+        __syncthreads();
+        if constexpr (G == 1 && U % 4 == 0)
+            tile_spmv_p8_rows<U, 1>(rp, pk.c8, s_toff, s_tval, pk.diag, pk.dcode, x, r0, r1, y, ytile);
+        else
+            tile_spmv_t<G, U>(rp, PackSrc<uint8_t>{pk.c8, s_toff, s_tval, pk.diag, pk.dcode}, x, r0, r1, y, ytile);
+        return;
+    }
+    with_entries(ci, val, rval, pk, [&](const auto& src) { tile_spmv_t<G, U>(rp, src, x, r0, r1, y, ytile); });
 }
 
 // Projection of iteration j on one tile.  FROM_Y: the sparse product already ran (k_yspmv)
@@ -244,7 +361,7 @@ __device__ __forceinline__ void tile_spmv(const int* __restrict__ rp, const int*
 template <int RPT, int G, int U, bool FROM_Y>
 __device__ __forceinline__ void project_body(const int* __restrict__ rp, const int* __restrict__ ci,
                                              const double2* __restrict__ val, const double* __restrict__ rval,
-                                             const double2* __restrict__ V,
+                                             const Packed& pk, const double2* __restrict__ V,
                                              int64_t ld, int dim, int j, double2* __restrict__ y,
                                              const DevState* __restrict__ st, const RedBuf& rb, int tile) {
     constexpr int R = kBlock * RPT;
@@ -257,7 +374,7 @@ __device__ __forceinline__ void project_body(const int* __restrict__ rp, const i
     const double2* __restrict__ x = V + (int64_t)j * ld;
 
     if (!FROM_Y) {
-        tile_spmv<G, U>(rp, ci, val, rval, x, r0, r1, y, ytile);
+        tile_spmv<G, U>(rp, ci, val, rval, pk, x, r0, r1, y, ytile);
         __syncthreads();
     }
     // Rows past the end of a ragged tile read row r1 - 1 and are weighted by zero, so the loads
@@ -328,21 +445,21 @@ __device__ __forceinline__ void project_body(const int* __restrict__ rp, const i
 template <int RPT, int G, int U, bool FROM_Y>
 __global__ __launch_bounds__(kBlock) void k_project(const int* __restrict__ rp, const int* __restrict__ ci,
                                                      const double2* __restrict__ val, const double* __restrict__ rval,
-                                                     const double2* __restrict__ V, int64_t ld, int dim, int j,
-                                                     double2* __restrict__ y, const DevState* __restrict__ st,
+                                                     Packed pk, const double2* __restrict__ V, int64_t ld, int dim,
+                                                     int j, double2* __restrict__ y, const DevState* __restrict__ st,
                                                      RedBuf rb) {
-    project_body<RPT, G, U, FROM_Y>(rp, ci, val, rval, V, ld, dim, j, y, st, rb, blockIdx.x);
+    project_body<RPT, G, U, FROM_Y>(rp, ci, val, rval, pk, V, ld, dim, j, y, st, rb, blockIdx.x);
 }
 
 // sparse product alone (split projection): y = H V[:, j] on the rows of one projection tile
 template <int RPT, int G, int U>
 __global__ __launch_bounds__(kBlock) void k_yspmv(const int* __restrict__ rp, const int* __restrict__ ci,
                                                    const double2* __restrict__ val, const double* __restrict__ rval,
-                                                   const double2* __restrict__ V, int64_t ld, int dim, int j,
-                                                   double2* __restrict__ y, const DevState* __restrict__ st) {
+                                                   Packed pk, const double2* __restrict__ V, int64_t ld, int dim,
+                                                   int j, double2* __restrict__ y, const DevState* __restrict__ st) {
     if (st->done || j >= st->k_limit) return;
     const int r0 = blockIdx.x * kBlock * RPT;
-    tile_spmv<G, U>(rp, ci, val, rval, V + (int64_t)j * ld, r0, min(r0 + kBlock * RPT, dim), y, nullptr);
+    tile_spmv<G, U>(rp, ci, val, rval, pk, V + (int64_t)j * ld, r0, min(r0 + kBlock * RPT, dim), y, nullptr);
 }
 
 // Batched projection.  Jobs that share H form a group; a group of one runs the fused kernel
@@ -376,12 +493,12 @@ __device__ __forceinline__ unsigned group_mask(const JobView* __restrict__ jobs,
 
 // y_v = H V_v[:, j] on rows [r0, r1) for every live vector: G lanes per row, U nonzeros in
 // flight each; results to y_v and, if ytile is given, to LDS (NV = 1).
-template <int G, int U, int NV, typename VT>
-__device__ __forceinline__ void group_spmv(const GroupView& gv, const VT* __restrict__ val, int r0, int r1,
+template <int G, int U, int NV, typename Src>
+__device__ __forceinline__ void group_spmv(const GroupView& gv, const Src& src, int r0, int r1,
                                            unsigned mask, const double2* const (&xs)[NV],
                                            double2* const (&ys)[NV], double2* ytile) {
+    using VT = typename Src::V;
     const int* __restrict__ rp = gv.rp;
-    const int* __restrict__ ci = gv.ci;
     const int tid = threadIdx.x;
     const int lg = tid % G, grp = tid / G;
     for (int r = r0 + grp; r < r1; r += kBlock / G) {
@@ -389,6 +506,7 @@ __device__ __forceinline__ void group_spmv(const GroupView& gv, const VT* __rest
 #pragma unroll
         for (int v = 0; v < NV; ++v) acc[v] = make_double2(0.0, 0.0);
         const int kb = rp[r], ke = rp[r + 1];
+        const Src rs = src.row(r);
         for (int k0 = kb + lg; k0 < ke; k0 += G * U) {
             VT vv[U];
             int cc[U];
@@ -396,8 +514,7 @@ __device__ __forceinline__ void group_spmv(const GroupView& gv, const VT* __rest
             for (int q = 0; q < U; ++q) {
                 const int k = k0 + q * G;
                 if (k < ke) {
-                    vv[q] = val[k];
-                    cc[q] = ci[k];
+                    rs.load(k, cc[q], vv[q]);
                 } else {
                     vv[q] = entry_zero<VT>();
                     cc[q] = -1;
@@ -433,7 +550,7 @@ __global__ __launch_bounds__(kBlock) void k_gproject(const JobView* __restrict__
                                                       const int2* __restrict__ items, int j) {
     const int2 it = items[blockIdx.x];
     const JobView& J = jobs[groups[it.x].job[0]];
-    project_body<RPT, G, U, false>(J.rp, J.ci, J.val, J.rval, J.V, J.ld, J.dim, j, J.y, J.st, J.rb, it.y);
+    project_body<RPT, G, U, false>(J.rp, J.ci, J.val, J.rval, J.pk, J.V, J.ld, J.dim, j, J.y, J.st, J.rb, it.y);
 }
 
 // multi-vector sparse product of a group: one workgroup per (group, tile)
@@ -448,8 +565,9 @@ __global__ __launch_bounds__(kBlock) void k_gspmm(const JobView* __restrict__ jo
     const unsigned mask = group_mask<NV>(jobs, gv, j, xs, ys);
     if (mask == 0) return;
     const int r0 = it.y * kBlock;
-    if (gv.rval) group_spmv<G, U, NV, double>(gv, gv.rval, r0, min(r0 + kBlock, gv.dim), mask, xs, ys, nullptr);
-    else group_spmv<G, U, NV, double2>(gv, gv.val, r0, min(r0 + kBlock, gv.dim), mask, xs, ys, nullptr);
+    with_entries(gv.ci, gv.val, gv.rval, gv.pk, [&](const auto& src) {
+        group_spmv<G, U, NV>(gv, src, r0, min(r0 + kBlock, gv.dim), mask, xs, ys, nullptr);
+    });
 }
 
 // projections after a multi-vector product: one workgroup per (job, tile of kBlock * RPT rows)
@@ -458,7 +576,7 @@ __global__ __launch_bounds__(kBlock) void k_bdots(const JobView* __restrict__ jo
                                                   int j) {
     const int2 it = items[blockIdx.x];
     const JobView& J = jobs[it.x];
-    project_body<RPT, 4, 4, true>(J.rp, J.ci, J.val, J.rval, J.V, J.ld, J.dim, j, J.y, J.st, J.rb, it.y);
+    project_body<RPT, 4, 4, true>(J.rp, J.ci, J.val, J.rval, J.pk, J.V, J.ld, J.dim, j, J.y, J.st, J.rb, it.y);
 }
 
 // ---------------------------------------------------- fold of the projection partials
@@ -789,18 +907,21 @@ __global__ __launch_bounds__(kBlock) void k_output(const double2* __restrict__ V
 }
 
 // ---------------------------------------------------------- standalone sparse product
-template <int G, typename VT>
-__global__ __launch_bounds__(kBlock) void k_spmv(const int* __restrict__ rp, const int* __restrict__ ci,
-                                                  const VT* __restrict__ val, const double2* __restrict__ x,
-                                                  double2* __restrict__ y, int dim, RedBuf rb, int rows_per_tile) {
-    __shared__ double lds[kWaves];
+template <int G, typename Src>
+__device__ __forceinline__ double2 spmv_rows(const int* __restrict__ rp, const Src& src,
+                                             const double2* __restrict__ x, double2* __restrict__ y, int r0, int r1) {
+    using VT = typename Src::V;
     const int tid = threadIdx.x, lg = tid % G, grp = tid / G;
-    const int r0 = blockIdx.x * rows_per_tile;
-    const int r1 = min(r0 + rows_per_tile, dim);
     double2 dot = make_double2(0.0, 0.0);
     for (int r = r0 + grp; r < r1; r += kBlock / G) {
         double2 acc = make_double2(0.0, 0.0);
-        for (int k = rp[r] + lg; k < rp[r + 1]; k += G) acc = entry_fma(val[k], x[ci[k]], acc);
+        const Src rs = src.row(r);
+        for (int k = rp[r] + lg; k < rp[r + 1]; k += G) {
+            int c;
+            VT v;
+            rs.load(k, c, v);
+            acc = entry_fma(v, x[c], acc);
+        }
 #pragma unroll
         for (int o = G / 2; o > 0; o >>= 1) {
             acc.x += __shfl_xor(acc.x, o);
@@ -811,6 +932,20 @@ __global__ __launch_bounds__(kBlock) void k_spmv(const int* __restrict__ rp, con
             dot = cfma_conj(x[r], acc, dot);
         }
     }
+    return dot;
+}
+
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_spmv(const int* __restrict__ rp, const int* __restrict__ ci,
+                                                  const double2* __restrict__ val, const double* __restrict__ rval,
+                                                  Packed pk, const double2* __restrict__ x,
+                                                  double2* __restrict__ y, int dim, RedBuf rb, int rows_per_tile) {
+    __shared__ double lds[kWaves];
+    const int tid = threadIdx.x;
+    const int r0 = blockIdx.x * rows_per_tile;
+    const int r1 = min(r0 + rows_per_tile, dim);
+    double2 dot = make_double2(0.0, 0.0);
+    with_entries(ci, val, rval, pk, [&](const auto& src) { dot = spmv_rows<G>(rp, src, x, y, r0, r1); });
     const double sx = block_sum(dot.x, lds);
     const double sy = block_sum(dot.y, lds);
     if (tid == 0) rb.part[blockIdx.x] = make_double2(sx, sy);
@@ -890,6 +1025,20 @@ __global__ __launch_bounds__(kBlock) void k_expand_real(const double* __restrict
                                                          int64_t n) {
     for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < n; k += (int64_t)gridDim.x * kBlock)
         val[k] = make_double2(rval[k], 0.0);
+}
+
+// one thread per row: columns and values of the row's packed entries
+__global__ __launch_bounds__(kBlock) void k_expand_packed(const int* __restrict__ rp, Packed pk, int dim,
+                                                          int* __restrict__ col, double2* __restrict__ val) {
+    for (int r = blockIdx.x * kBlock + threadIdx.x; r < dim; r += gridDim.x * kBlock)
+        with_entries(nullptr, nullptr, nullptr, pk, [&](const auto& src) {
+            const auto rs = src.row(r);
+            for (int k = rp[r]; k < rp[r + 1]; ++k) {
+                typename std::decay_t<decltype(src)>::V v;
+                rs.load(k, col[k], v);
+                val[k] = as_complex(v);
+            }
+        });
 }
 
 __global__ __launch_bounds__(kBlock) void k_real_part(const double2* __restrict__ val, double* __restrict__ rval,
@@ -1024,22 +1173,36 @@ hipError_t launch_copy(const double2* src, double2* dst, int dim, hipStream_t s)
     return hipGetLastError();
 }
 
+// Calls f with the (lanes per row, nonzeros per lane) of a supported sparse-product shape.
+template <typename F>
+void by_spmv_shape(int g, int u, F&& f) {
+    using std::integral_constant;
+    if (g == 8) f(integral_constant<int, 8>{}, integral_constant<int, 2>{});
+    else if (g == 2) f(integral_constant<int, 2>{}, integral_constant<int, 8>{});
+    else if (g == 1 && u == 16) f(integral_constant<int, 1>{}, integral_constant<int, 16>{});
+    else if (g == 1) f(integral_constant<int, 1>{}, integral_constant<int, 8>{});
+    else if (u == 1) f(integral_constant<int, 4>{}, integral_constant<int, 1>{});
+    else f(integral_constant<int, 4>{}, integral_constant<int, 4>{});
+}
+
 hipError_t launch_project(const Tiling& tl, const Csr& H, const double2* V, int64_t ld, int j, double2* y,
                           const DevState* st, const RedBuf& rb, hipStream_t s, hipEvent_t start, hipEvent_t done) {
     return by_rpt_p(tl.rpt_p, [&](auto r) {
         constexpr int RPT = decltype(r)::value;
         const dim3 grid(tl.n_tiles_p);
-        if (tl.split) {  // the sparse product keeps one row per thread; rpt_p shapes the projections
-            const dim3 g1((H.dim + kBlock - 1) / kBlock);
-            if (tl.g == 8) launch_timed(k_yspmv<1, 8, 2>, g1, s, start, nullptr, H.row_ptr, H.col, H.val, H.rval, V, ld, H.dim, j, y, st);
-            else if (tl.u == 1) launch_timed(k_yspmv<1, 4, 1>, g1, s, start, nullptr, H.row_ptr, H.col, H.val, H.rval, V, ld, H.dim, j, y, st);
-            else launch_timed(k_yspmv<1, 4, 4>, g1, s, start, nullptr, H.row_ptr, H.col, H.val, H.rval, V, ld, H.dim, j, y, st);
-            launch_timed(k_project<RPT, 4, 4, true>, grid, s, nullptr, done, H.row_ptr, H.col, H.val, H.rval, V, ld, H.dim, j, y, st, rb);
-        } else {
-            if (tl.g == 8) launch_timed(k_project<RPT, 8, 2, false>, grid, s, start, done, H.row_ptr, H.col, H.val, H.rval, V, ld, H.dim, j, y, st, rb);
-            else if (tl.u == 1) launch_timed(k_project<RPT, 4, 1, false>, grid, s, start, done, H.row_ptr, H.col, H.val, H.rval, V, ld, H.dim, j, y, st, rb);
-            else launch_timed(k_project<RPT, 4, 4, false>, grid, s, start, done, H.row_ptr, H.col, H.val, H.rval, V, ld, H.dim, j, y, st, rb);
-        }
+        by_spmv_shape(tl.g, tl.u, [&](auto g, auto u) {
+            constexpr int G = decltype(g)::value, U = decltype(u)::value;
+            if (tl.split) {  // the sparse product keeps one row per thread; rpt_p shapes the projections
+                const dim3 g1((H.dim + kBlock - 1) / kBlock);
+                launch_timed(k_yspmv<1, G, U>, g1, s, start, nullptr, H.row_ptr, H.col, H.val, H.rval, H.pk, V, ld,
+                             H.dim, j, y, st);
+                launch_timed(k_project<RPT, 4, 4, true>, grid, s, nullptr, done, H.row_ptr, H.col, H.val, H.rval, H.pk,
+                             V, ld, H.dim, j, y, st, rb);
+            } else {
+                launch_timed(k_project<RPT, G, U, false>, grid, s, start, done, H.row_ptr, H.col, H.val, H.rval, H.pk,
+                             V, ld, H.dim, j, y, st, rb);
+            }
+        });
     });
 }
 
@@ -1081,8 +1244,7 @@ hipError_t launch_scale_columns(const double2* src, double2* dst, int64_t ld, in
 
 hipError_t launch_spmv_only(const Tiling& tl, const Csr& H, const double2* x, double2* y, DevState* st,
                             const RedBuf& rb, hipStream_t s) {
-    if (H.rval) k_spmv<4, double><<<tl.n_tiles_p, kBlock, 0, s>>>(H.row_ptr, H.col, H.rval, x, y, H.dim, rb, kBlock * tl.rpt_p);
-    else k_spmv<4, double2><<<tl.n_tiles_p, kBlock, 0, s>>>(H.row_ptr, H.col, H.val, x, y, H.dim, rb, kBlock * tl.rpt_p);
+    k_spmv<4><<<tl.n_tiles_p, kBlock, 0, s>>>(H.row_ptr, H.col, H.val, H.rval, H.pk, x, y, H.dim, rb, kBlock * tl.rpt_p);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_sum_part<<<1, kBlock, 0, s>>>(st, rb);
@@ -1105,6 +1267,12 @@ hipError_t launch_real_part(const double2* val, double* rval, int64_t n, hipStre
 hipError_t launch_expand_real(const double* rval, double2* val, int64_t n, hipStream_t s) {
     const int blocks = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, 8192);
     k_expand_real<<<blocks, kBlock, 0, s>>>(rval, val, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_expand_packed(const int* row_ptr, const Packed& pk, int dim, int* col, double2* val, hipStream_t s) {
+    const int blocks = (int)std::min<int64_t>(((int64_t)dim + kBlock - 1) / kBlock, 8192);
+    k_expand_packed<<<blocks, kBlock, 0, s>>>(row_ptr, pk, dim, col, val);
     return hipGetLastError();
 }
 

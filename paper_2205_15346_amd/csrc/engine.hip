@@ -196,6 +196,7 @@ JobView job_view(te_engine_s* e, const JobRec& j, int rpt_u) {
     v.ci = j.h->csr.col;
     v.val = j.h->csr.val;
     v.rval = j.h->csr.rval;
+    v.pk = j.h->csr.pk;
     v.V = (double2*)(base + L.v);
     v.y = (double2*)(base + L.y);
     v.st = e->states + j.slot;
@@ -437,6 +438,7 @@ te_status build_plan(te_engine_s* e) {
         gv.ci = j0.h->csr.col;
         gv.val = j0.h->csr.val;
         gv.rval = j0.h->csr.rval;
+        gv.pk = j0.h->csr.pk;
         gv.dim = j0.dim;
         gv.nv = (int)g.size();
         for (int q = 0; q < kMaxGroup; ++q) gv.job[q] = q < gv.nv ? g[(size_t)q] : 0;
@@ -531,7 +533,7 @@ void round_bytes(const te_engine_s* e, const Plan& p, const std::vector<int>& kk
                 }
                 if (j < k) pr->bytes[TE_KERNEL_UPDATE] += 16.0 * d * (cols + 1) + ((j + 1 < m) ? 16.0 * d : 0.0);
             }
-            if (any) pr->bytes[TE_KERNEL_PROJECT] += csr_entry_bytes(j0.h->csr) * nnz + 4.0 * (d + 1);
+            if (any) pr->bytes[TE_KERNEL_PROJECT] += csr_entries_bytes(j0.h->csr) + 4.0 * (d + 1);
         }
         for (int q : g)
             if (kk[(size_t)q] > 0) pr->bytes[TE_KERNEL_COMBINE] += 16.0 * d * (kk[(size_t)q] + 1);

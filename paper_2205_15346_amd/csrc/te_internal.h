@@ -82,12 +82,26 @@ struct RedBuf {
 };
 
 // -------------------------------------------------------------------- batched engine
+// Packed entries: entry k of row r holds a code q; q stands for column r + toff[q] and value
+// tval[q], except q = dcode, the row's diagonal: column r, value (diag[r], 0).  Codes are one
+// byte when there are at most 255 distinct (column offset, value) pairs off the diagonal, else
+// two bytes.
+struct Packed {
+    const uint8_t* c8 = nullptr;    // 1-byte codes, or
+    const uint16_t* c16 = nullptr;  // 2-byte codes (at most one is set)
+    const int* toff = nullptr;      // [dcode + 1] column offsets, toff[dcode] = 0
+    const double2* tval = nullptr;  // [dcode + 1] values
+    const double* diag = nullptr;   // [dim] real diagonal (0 where a row has none)
+    int dcode = 0;
+};
+
 // One evolution job of a batched round: its matrix, basis, state and reduction scratch.
 struct JobView {
     const int* rp;
     const int* ci;
     const double2* val;  // complex entries, or
-    const double* rval;  // real entries (exactly one is set)
+    const double* rval;  // real entries, or
+    Packed pk;           // packed entries (exactly one of the three is set)
     double2* V;          // basis columns, leading dimension ld
     double2* y;          // raw product H V[:, j]
     DevState* st;
@@ -107,7 +121,8 @@ struct GroupView {
     const int* rp;
     const int* ci;
     const double2* val;    // complex entries, or
-    const double* rval;    // real entries (exactly one is set)
+    const double* rval;    // real entries, or
+    Packed pk;             // packed entries (exactly one of the three is set)
     int dim;
     int nv;                // jobs in the group (1..kMaxGroup)
     int job[kMaxGroup];    // indices into the round's JobView array
@@ -211,18 +226,28 @@ __device__ __forceinline__ double block_max(double v, double* lds /* kWaves */) 
 // ----------------------------------------------------------------------- launchers
 struct Workspace;  // defined in api.hip
 
-// Exactly one of val (complex entries) and rval (real entries) is set.
+// Exactly one of val (complex entries with columns), rval (real entries with columns) and
+// pk (packed entries, col unset) is set.
 struct Csr {
     const int* row_ptr;
     const int* col;
     const double2* val;
     const double* rval;
+    Packed pk;
     int dim;
     int64_t nnz;
 };
 
-// bytes streamed per stored entry by a sparse product: value + column index
-inline double csr_entry_bytes(const Csr& c) { return c.rval ? 12.0 : 20.0; }
+inline bool is_packed(const Packed& p) { return p.c8 != nullptr || p.c16 != nullptr; }
+
+// bytes a sparse product streams for the stored entries (row pointers and vectors aside):
+// value + column index per entry, or a code per entry and the real diagonal per row
+inline double csr_entries_bytes(const Csr& c) {
+    const double nnz = (double)c.nnz, d = (double)c.dim;
+    if (c.pk.c8) return 1.0 * nnz + 8.0 * d;
+    if (c.pk.c16) return 2.0 * nnz + 8.0 * d;
+    return (c.rval ? 12.0 : 20.0) * nnz;
+}
 
 // Row tiling of the row-parallel kernels.  The projection kernel's shape is chosen per matrix
 // by the autotuner: g lanes share a row of the sparse product, each keeping u nonzeros in
@@ -264,6 +289,8 @@ hipError_t launch_validate(const Csr& H, int check_hermitian, int* err, double* 
 hipError_t launch_norm1(const double* rowsum, int dim, double* out, hipStream_t s);
 hipError_t launch_real_part(const double2* val, double* rval, int64_t n, hipStream_t s);
 hipError_t launch_expand_real(const double* rval, double2* val, int64_t n, hipStream_t s);
+// Columns and complex values of packed entries (inverse of the packing).
+hipError_t launch_expand_packed(const int* row_ptr, const Packed& pk, int dim, int* col, double2* val, hipStream_t s);
 
 // Device construction of the paper's exemplary Hamiltonian (models.hip): sizes, parameters and
 // device tables prepared by te_hamiltonian_create_memory_burden.
@@ -345,6 +372,10 @@ struct te_hamiltonian_s {
     int* col = nullptr;
     double2* val = nullptr;
     double* rval = nullptr;
+    void* code = nullptr;      // packed entries: codes, table and diagonal
+    int* toff = nullptr;
+    double2* tval = nullptr;
+    double* diag = nullptr;
     double norm1 = 0.0;
     std::mutex mu;
     te::Workspace* ws = nullptr;

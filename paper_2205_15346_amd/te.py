@@ -29,6 +29,9 @@ TE_WARN_QUADRATURE = 2
 TE_PTR_DEVICE = 1
 TE_CHECK_HERMITIAN = 2
 TE_STORE_COMPLEX = 4
+TE_STORE_CSR = 8
+TE_STORAGE_COMPLEX, TE_STORAGE_REAL, TE_STORAGE_PACKED8, TE_STORAGE_PACKED16 = 0, 1, 2, 3
+STORAGE_NAMES = {0: "complex", 1: "real", 2: "packed8", 3: "packed16"}
 TE_MAX_KRYLOV = 64
 
 
@@ -150,6 +153,7 @@ _SIGS = {
     "te_hamiltonian_destroy": (_I, [_P]),
     "te_hamiltonian_info": (_I, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), _PD]),
     "te_hamiltonian_real_values": (_I, [_P, _PI]),
+    "te_hamiltonian_storage": (_I, [_P, _PI]),
     "te_hamiltonian_copy_csr": (_I, [_P, _P, _P, _P, ctypes.c_uint32, _P]),
     "te_memory_burden_defaults": (None, [ctypes.c_void_p]),
     "te_hamiltonian_create_memory_burden": (_I, [ctypes.POINTER(_P), ctypes.c_void_p, ctypes.POINTER(_I64), _P]),
@@ -246,6 +250,9 @@ class Hamiltonian:
         rv = _I()
         _check(_lib.te_hamiltonian_real_values(self._h, ctypes.byref(rv)))
         self.real_values = bool(rv.value)  # entries stored as real (8 B) rather than complex
+        sk = ctypes.c_int32()
+        _check(_lib.te_hamiltonian_storage(self._h, ctypes.byref(sk)))
+        self.storage = STORAGE_NAMES[sk.value]  # "complex", "real", "packed8" or "packed16"
 
     @property
     def handle(self):
@@ -272,12 +279,14 @@ class Hamiltonian:
 
 
 def te_hamiltonian_create(row_ptr, col_idx, values, check_hermitian=False, stream=None,
-                          store_complex=False) -> Hamiltonian:
+                          store_complex=False, store_csr=False) -> Hamiltonian:
     """From host NumPy arrays (int32, int32, complex128) or CUDA tensors of the same dtypes.
-    A matrix whose imaginary parts are all zero is stored with real entries unless
-    store_complex is set."""
+    Entries are packed (codes into a table of (column offset, value) pairs) when few distinct
+    pairs occur, unless store_csr is set; else a matrix whose imaginary parts are all zero is
+    stored with real entries unless store_complex is set."""
     import torch
-    flags = (TE_CHECK_HERMITIAN if check_hermitian else 0) | (TE_STORE_COMPLEX if store_complex else 0)
+    flags = ((TE_CHECK_HERMITIAN if check_hermitian else 0) | (TE_STORE_COMPLEX if store_complex else 0)
+             | (TE_STORE_CSR if store_csr else 0))
     keep = []
     if isinstance(values, torch.Tensor):
         flags |= TE_PTR_DEVICE

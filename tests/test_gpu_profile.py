@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from tests.gpu_util import announce, hamiltonian, lib, to_dev, to_host
+from tests.gpu_util import announce, lib, to_dev, to_host
 from workloads.csr import CSR
 
 pytestmark = pytest.mark.gpu
@@ -24,21 +24,22 @@ def _evolve(te, h, x, t, tol, flags=0):
     return to_host(v), (res.steps, res.matvecs, res.err_bound, res.num_err_estimate)
 
 
-def expected_project_bytes(H, entry_bytes, steps):
+def expected_project_bytes(H, kind, steps):
     d, nnz = float(H.dim), float(H.nnz)
-    per_restart = sum(entry_bytes * nnz + 4.0 * (d + 1) + 16.0 * d * (j + 2) for j in range(M))
+    entries = {"complex": 20.0 * nnz, "real": 12.0 * nnz, "packed8": 1.0 * nnz + 8.0 * d}[kind]
+    per_restart = sum(entries + 4.0 * (d + 1) + 16.0 * d * (j + 2) for j in range(M))
     return steps * per_restart
 
 
-@pytest.mark.parametrize("real", [False, True])
-def test_profiled_solve_is_bitwise_the_graph_solve(real):
-    announce(f"profile vs graph, real entries {real}")
+@pytest.mark.parametrize("kind", ["complex", "real", "packed8"])
+def test_profiled_solve_is_bitwise_the_graph_solve(kind):
+    announce(f"profile vs graph, storage {kind}")
     te = lib()
     H, v0 = W.xxz_chain(13, seed=31)
-    if real:
+    if kind == "real":
         H = CSR(H.dim, H.row_ptr, H.col, np.ascontiguousarray(H.val.real.astype(np.complex128)), "xxz_re")
-    with hamiltonian(H) as h:
-        assert h.real_values == real
+    with te.te_hamiltonian_create(H.row_ptr, H.col, H.val, store_csr=kind != "packed8") as h:
+        assert h.storage == kind
         te.te_set_tuning(h, 8, 2, 4, 2, 1)
         x = to_dev(v0)
         vg, rg = _evolve(te, h, x, 12.0, 1e-8)
@@ -58,7 +59,7 @@ def test_profiled_solve_is_bitwise_the_graph_solve(real):
     assert prof["project"]["launches"] == steps * M == matvecs
     assert prof["update"]["launches"] == steps * M and prof["fold"]["launches"] == steps * M
     assert prof["step"]["launches"] == steps and prof["combine"]["launches"] == steps
-    want = expected_project_bytes(H, 12.0 if real else 20.0, steps)
+    want = expected_project_bytes(H, kind, steps)
     assert prof["project"]["bytes"] == pytest.approx(want, rel=1e-12)
     secs = [prof[k]["seconds"] for k in te.KERNEL_CLASSES]
     assert all(s > 0 for s in secs)
