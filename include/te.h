@@ -401,8 +401,8 @@ typedef struct {
     int32_t m;                      /* Krylov dimension, 2..TE_MAX_KRYLOV (clamped per job to dim) */
     int32_t max_jobs;               /* resident jobs at most, 1..16384 */
     uint64_t hbm_budget;            /* bytes of device memory for job workspaces, allocated once */
-    int32_t lanes_per_row;          /* sparse-product shape: 4 or 8 lanes per row; 0 = autotune */
-    int32_t nnz_per_lane;           /* 1 or 4 with 4 lanes, 2 with 8 lanes */
+    int32_t lanes_per_row;          /* sparse-product shape: 1, 4 or 8 lanes per row; 0 = autotune */
+    int32_t nnz_per_lane;           /* 8 with 1 lane, 1 or 4 with 4 lanes, 2 with 8 lanes */
     int32_t rows_per_thread;        /* projections: 1, 2 or 4 rows per thread; 0 = 4 */
     int32_t update_rows_per_thread; /* update and recombination: 1 or 2; 0 = 2 */
     uint32_t flags;                 /* TE_ENGINE_* */

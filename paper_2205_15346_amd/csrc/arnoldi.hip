@@ -1091,7 +1091,7 @@ static void launch_timed(void (*kernel)(KArgs...), dim3 grid, hipStream_t s, hip
 static int grid_for(int dim) { return (int)std::min<int64_t>(((int64_t)dim + kBlock - 1) / kBlock, 4096); }
 
 // ----------------------------------------------------------------- batched launchers
-bool gproject_supported(int g, int u) { return (g == 4 && (u == 1 || u == 4)) || (g == 8 && u == 2); }
+bool gproject_supported(int g, int u) { return (g == 4 && (u == 1 || u == 4)) || (g == 8 && u == 2) || (g == 1 && u == 8); }
 
 template <int RPT, int G, int U>
 static void gproject_nv(int nv_class, dim3 grid, hipStream_t s, const JobView* jobs, const GroupView* groups,
@@ -1113,6 +1113,7 @@ hipError_t launch_gproject(int g, int u, int rpt, int nv_class, const JobView* j
     return by_rpt_p(rpt, [&](auto r) {
         constexpr int RPT = decltype(r)::value;
         if (g == 8) gproject_nv<RPT, 8, 2>(nv_class, grid, s, jobs, groups, items, j);
+        else if (g == 1) gproject_nv<RPT, 1, 8>(nv_class, grid, s, jobs, groups, items, j);
         else if (u == 1) gproject_nv<RPT, 4, 1>(nv_class, grid, s, jobs, groups, items, j);
         else gproject_nv<RPT, 4, 4>(nv_class, grid, s, jobs, groups, items, j);
     });

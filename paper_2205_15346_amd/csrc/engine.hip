@@ -251,7 +251,7 @@ hipError_t enqueue_round(te_engine_s* e, const Plan& p, hipStream_t s, std::vect
 // it only writes the product vectors and partials, which the first round overwrites.
 te_status autotune(te_engine_s* e, const Plan& p) {
     const int J = std::min(p.m / 2, p.m - 1);  // mid-restart: the mean cost over j = 0..m-1
-    const int shapes[3][2] = {{4, 1}, {4, 4}, {8, 2}};
+    const int shapes[4][2] = {{4, 1}, {4, 4}, {8, 2}, {1, 8}};
     hipEvent_t e0, e1;
     EHIP(hipEventCreate(&e0));
     EHIP(hipEventCreate(&e1));
@@ -734,7 +734,7 @@ te_status check_config(const te_engine_config& c) {
     if (c.m > TE_MAX_KRYLOV) return set_error(TE_ERR_UNSUPPORTED, "m > TE_MAX_KRYLOV");
     if (c.max_jobs < 1 || c.max_jobs > kMaxEngineJobs) return set_error(TE_ERR_INVALID_ARG, "max_jobs out of range");
     if (c.lanes_per_row != 0 && !gproject_supported(c.lanes_per_row, c.nnz_per_lane))
-        return set_error(TE_ERR_INVALID_ARG, "unsupported projection shape (4 lanes with 1 or 4 nonzeros, 8 with 2)");
+        return set_error(TE_ERR_INVALID_ARG, "unsupported projection shape (4 lanes with 1 or 4 nonzeros, 8 with 2, 1 with 8)");
     if (c.update_rows_per_thread < 0 || c.update_rows_per_thread > 2)
         return set_error(TE_ERR_INVALID_ARG, "update_rows_per_thread must be 0, 1 or 2");
     if (c.rows_per_thread != 0 && c.rows_per_thread != 1 && c.rows_per_thread != 2 && c.rows_per_thread != 4)

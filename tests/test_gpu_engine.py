@@ -52,7 +52,8 @@ def mixed_groups():
     return groups
 
 
-@pytest.mark.parametrize("tune", [((4, 4), 2, 2), ((8, 2), 1, 1), ((4, 1), 2, 1), ((8, 2), 4, 2)])
+@pytest.mark.parametrize("tune", [((4, 4), 2, 2), ((8, 2), 1, 1), ((4, 1), 2, 1), ((8, 2), 4, 2), ((1, 8), 4, 2),
+                                  ((1, 8), 1, 1)])
 def test_batch_bitwise_equals_alone(mixed_groups, tune):
     te = lib()
     shape, rpt, rpt_u = tune
@@ -97,7 +98,7 @@ def test_batch_autotuned_agrees_with_alone(mixed_groups):
     announce("batch autotuned")
     outs, results, stats = te.te_batch_run([(h, d, t, tol) for h, d, (_, _, t, tol) in zip(hs, dev, mixed_groups)],
                                            m=M)
-    assert (stats.tuning.lanes_per_row, stats.tuning.nnz_per_lane) in [(4, 1), (4, 4), (8, 2)]
+    assert (stats.tuning.lanes_per_row, stats.tuning.nnz_per_lane) in [(4, 1), (4, 4), (8, 2), (1, 8)]
     assert stats.tuning.project_us > 0
     i = 0
     for gi, (h, d, (_, _, t, tol)) in enumerate(zip(hs, dev, mixed_groups)):
