@@ -324,19 +324,33 @@ def bench_paper_model(te, torch, dev):
     x[idx] = 1.0  # eq. initialStateSimple
     dim, nnz = h.dim, h.nnz
     log(f"[bench] paper model built on the device in {build_s:.3f} s (host builder {host_build_s:.1f} s)")
-    te.te_evolve(h, x, 10.0, 1e-7, 40)  # warm-up and autotune
-    times = []
-    for _ in range(3):
-        torch.cuda.synchronize()
-        s0 = time.perf_counter()
-        _, res = te.te_evolve(h, x, 10.0, 1e-7, 40)
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - s0)
+    def timed():
+        te.te_evolve(h, x, 10.0, 1e-7, 40)  # warm-up and autotune
+        times = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            s0 = time.perf_counter()
+            out, res = te.te_evolve(h, x, 10.0, 1e-7, 40)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - s0)
+        return sum(times) / len(times), out, res
+
+    storage_built = h.storage
+    sec_csr, out_csr, res_csr = timed()
+    torch.cuda.synchronize()
+    p0 = time.perf_counter()
+    storage = te.te_hamiltonian_pack(h)  # value codes: the couplings take a few hundred values
+    pack_s = time.perf_counter() - p0
+    sec, out, res = timed()
     h.destroy()
-    sec = sum(times) / len(times)
-    log(f"[bench] paper model d={dim}: {sec:.3f} s per solve, restarts={res.steps}, bound={res.err_bound:.2e}, "
+    agree = float((out - out_csr).norm()) / (res.err_bound + res_csr.err_bound + res.num_err_estimate
+                                             + res_csr.num_err_estimate)
+    log(f"[bench] paper model d={dim}: {sec:.3f} s per solve ({storage}; {sec_csr:.3f} s as {storage_built} "
+        f"entries, packed in {pack_s:.2f} s), restarts={res.steps}, bound={res.err_bound:.2e}, "
         f"roundoff estimate={res.num_err_estimate:.2e}")
-    return {"dim": dim, "nnz": nnz, "t": 10.0, "tol": 1e-7, "m": 40, "seconds_per_solve": sec,
+    return {"dim": dim, "nnz": nnz, "t": 10.0, "tol": 1e-7, "m": 40, "seconds_per_solve": sec, "storage": storage,
+            "seconds_per_solve_unpacked": sec_csr, "storage_unpacked": storage_built, "pack_seconds": pack_s,
+            "diff_packed_vs_unpacked_over_bounds_and_roundoff": agree,
             "restarts": res.steps, "err_bound": res.err_bound, "num_err_estimate": res.num_err_estimate,
             "warnings": res.warnings, "build_seconds_device": build_s, "build_seconds_host_builder": host_build_s,
             "paper_context": {"seconds_one_cpu_thread_i9_9900K": 353.0, "num_err_estimate": 3.2e-6}}

@@ -156,8 +156,10 @@ const char* te_last_error(void);
  * 255 pairs) or 2-byte code into a table of the pairs, plus the real diagonal per row, and
  * drops the column indices and values: a sparse product then streams 1 or 2 bytes per entry
  * and 8 per row instead of 20 (or 12) per entry, and gives bitwise the values of the CSR it
- * was packed from (same entries, same order).  The test is one host pass over the entries
- * (read back from the device in chunks).  TE_STORE_CSR keeps the CSR regardless. */
+ * was packed from (same entries, same order).  With more pairs but at most 65535 distinct
+ * values off the diagonal (the paper's model: its couplings), the columns stay and the codes
+ * index the values ("value codes": 5 or 6 bytes per entry).  The test is one host pass over
+ * the entries (read back from the device in chunks).  TE_STORE_CSR keeps the CSR regardless. */
 te_status te_hamiltonian_create(te_hamiltonian* out, int64_t dim, int64_t nnz,
                                 const int32_t* row_ptr, const int32_t* col_idx,
                                 const te_c128* values, uint32_t flags, void* stream);
@@ -170,9 +172,18 @@ enum {
     TE_STORAGE_COMPLEX = 0,   /* column + complex value per entry (20 bytes) */
     TE_STORAGE_REAL = 1,      /* column + real value per entry (12 bytes) */
     TE_STORAGE_PACKED8 = 2,   /* 1-byte code per entry + real diagonal per row */
-    TE_STORAGE_PACKED16 = 3   /* 2-byte code per entry + real diagonal per row */
+    TE_STORAGE_PACKED16 = 3,  /* 2-byte code per entry + real diagonal per row */
+    TE_STORAGE_CODED8 = 4,    /* column + 1-byte value code per entry + real diagonal per row */
+    TE_STORAGE_CODED16 = 5    /* column + 2-byte value code per entry + real diagonal per row */
 };
 te_status te_hamiltonian_storage(te_hamiltonian h, int32_t* kind);
+
+/* Packs the entries of a handle held as CSR (one built on the device, or created with
+ * TE_STORE_CSR) as te_hamiltonian_create would; a no-op for a packed handle or a matrix that
+ * does not pack.  *kind (may be NULL) receives the storage afterwards.  The handle's kernel
+ * shape is tuned again on its next use.  Not while the handle is in use by a solve, a batch or
+ * an engine.  Synchronous on `stream`. */
+te_status te_hamiltonian_pack(te_hamiltonian h, int32_t* kind, void* stream);
 
 /* Copies the handle's CSR out: row_ptr[dim+1], col_idx[nnz], values[nnz] (complex; real
  * entries are returned with zero imaginary parts).  Device pointers with TE_PTR_DEVICE, else

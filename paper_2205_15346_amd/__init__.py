@@ -12,7 +12,7 @@ _TE_NAMES = ("Hamiltonian", "TEError", "te_arnoldi", "te_default_options", "te_e
              "te_hamiltonian_create", "te_last_profile", "te_autotune", "te_get_tuning", "te_set_tuning", "te_spmv", "te_step_search", "te_tridiag_eig",
              "te_workspace_bytes", "te_job_footprint", "te_evolve_sampled", "Engine", "te_batch_run", "te_engine_default_config",
              "te_hamiltonian_create_memory_burden", "te_memory_burden_defaults", "te_hamiltonian_copy_csr",
-             "te_hamiltonian_create_bose_chain")
+             "te_hamiltonian_create_bose_chain", "te_hamiltonian_pack")
 
 
 def __getattr__(name):

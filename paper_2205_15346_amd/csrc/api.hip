@@ -308,7 +308,8 @@ te_status retile(te_hamiltonian h, Workspace* w, const Tiling& t) {
 // "gfx950/<storage> dim nnz m": the best shape depends on how the entries are stored
 std::string tune_key(te_hamiltonian h, int m) {
     const Csr& c = h->csr;
-    const char* storage = c.pk.c8 ? "packed8" : c.pk.c16 ? "packed16" : c.rval ? "real" : "complex";
+    const char* storage = c.pk.c8 ? (c.pk.col ? "coded8" : "packed8") : c.pk.c16 ? (c.pk.col ? "coded16" : "packed16")
+                          : c.rval ? "real" : "complex";
     return std::string("gfx950/") + storage + " " + std::to_string(c.dim) + " " + std::to_string(c.nnz) + " " +
            std::to_string(m);
 }
@@ -542,10 +543,11 @@ static te_status keep_real_entries(te_hamiltonian h, hipStream_t s) {
 }
 
 // Packing of the stored entries (te::Packed).  One host pass over the entries, read back from
-// the device in chunks, collects the distinct (column - row, value) pairs off the diagonal in
-// an open-addressing table (values compared bit for bit).  The matrix stays in CSR form
-// (*packed = false) when there are more than 65535 pairs, a diagonal entry has an imaginary
-// part other than +0, or a row stores its diagonal twice.
+// the device in chunks, collects the distinct (column - row, value) pairs and the distinct
+// values off the diagonal in two open-addressing tables (values compared bit for bit).  At most
+// 65535 pairs: codes of pairs, no columns.  Else at most 65535 values: value codes beside the
+// columns.  The matrix stays in CSR form (*packed = false) when both are exceeded, a diagonal
+// entry has an imaginary part other than +0, or a row stores its diagonal twice.
 namespace {
 
 struct PairKey {
@@ -561,10 +563,36 @@ inline uint64_t mix64(uint64_t x) {  // the splitmix64 finaliser
     return x ^ (x >> 31);
 }
 
-constexpr int kMaxPairs = 65535;
-constexpr int kPairSlots = 1 << 17;  // load factor <= 1/2
+constexpr int kMaxCodes = 65535;     // codes 0..65534 off the diagonal, 65535 for the diagonal
+constexpr int kCodeSlots = 1 << 17;  // load factor <= 1/2
 constexpr int64_t kPackChunk = (int64_t)1 << 22;
 constexpr size_t kCodePad = 64;  // >= the largest batch of codes + 4 bytes
+
+// Distinct keys -> codes in first-seen order; full once kMaxCodes keys are held.
+struct CodeTable {
+    std::vector<int32_t> slot;
+    std::vector<PairKey> keys;
+    std::vector<int> off;
+    std::vector<double2> val;
+    bool full = false;
+    CodeTable() : slot(kCodeSlots, -1), keys(kCodeSlots) {}
+    // code of the key, or -1 when the table is (or just became) full
+    int code(int32_t o, uint64_t re, uint64_t im, double2 v) {
+        if (full) return -1;
+        uint32_t q = (uint32_t)mix64(((uint64_t)(uint32_t)o << 32) ^ mix64(re) ^ (mix64(im) * 3u)) & (kCodeSlots - 1);
+        while (slot[q] >= 0 && !(keys[q].off == o && keys[q].re == re && keys[q].im == im)) q = (q + 1) & (kCodeSlots - 1);
+        if (slot[q] >= 0) return slot[q];
+        if ((int)off.size() == kMaxCodes) {
+            full = true;
+            return -1;
+        }
+        slot[q] = (int32_t)off.size();
+        keys[q] = PairKey{o, re, im};
+        off.push_back(o);
+        val.push_back(v);
+        return slot[q];
+    }
+};
 
 }  // namespace
 
@@ -572,21 +600,22 @@ static te_status try_pack(te_hamiltonian h, hipStream_t s, bool* packed) {
     *packed = false;
     const int dim = h->csr.dim;
     const int64_t nnz = h->csr.nnz;
+    const bool real = h->csr.val == nullptr;  // real CSR entries (rval)
     std::vector<int> rp;
-    std::vector<uint16_t> code;
+    std::vector<uint16_t> pcode, vcode;  // codes of pairs, codes of values
     std::vector<double> diag;
     std::vector<int> cbuf;
     std::vector<double2> vbuf;
-    std::vector<int32_t> slot(kPairSlots, -1);
-    std::vector<PairKey> keys(kPairSlots);
-    std::vector<int> toff;
-    std::vector<double2> tval;
+    std::vector<double> rbuf;
+    CodeTable pairs, values;
     try {
         rp.resize((size_t)dim + 1);
-        code.resize((size_t)nnz);
+        pcode.resize((size_t)nnz);
+        vcode.resize((size_t)nnz);
         diag.assign((size_t)dim, 0.0);
         cbuf.resize((size_t)std::min(nnz, kPackChunk));
-        vbuf.resize((size_t)std::min(nnz, kPackChunk));
+        if (real) rbuf.resize((size_t)std::min(nnz, kPackChunk));
+        else vbuf.resize((size_t)std::min(nnz, kPackChunk));
     } catch (...) {
         return TE_OK;  // no host memory for the pass: keep CSR
     }
@@ -597,13 +626,14 @@ static te_status try_pack(te_hamiltonian h, hipStream_t s, bool* packed) {
     for (int64_t k0 = 0; k0 < nnz; k0 += kPackChunk) {
         const int64_t n = std::min(kPackChunk, nnz - k0);
         TE_HIP(hipMemcpyAsync(cbuf.data(), h->csr.col + k0, (size_t)n * sizeof(int), hipMemcpyDeviceToHost, s));
-        TE_HIP(hipMemcpyAsync(vbuf.data(), h->csr.val + k0, (size_t)n * sizeof(double2), hipMemcpyDeviceToHost, s));
+        if (real) TE_HIP(hipMemcpyAsync(rbuf.data(), h->csr.rval + k0, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, s));
+        else TE_HIP(hipMemcpyAsync(vbuf.data(), h->csr.val + k0, (size_t)n * sizeof(double2), hipMemcpyDeviceToHost, s));
         TE_HIP(hipStreamSynchronize(s));
         for (int64_t i = 0; i < n; ++i) {
             const int64_t k = k0 + i;
             while (rp[(size_t)r + 1] <= k) ++r;
             const int c = cbuf[(size_t)i];
-            const double2 v = vbuf[(size_t)i];
+            const double2 v = real ? make_double2(rbuf[(size_t)i], 0.0) : vbuf[(size_t)i];
             uint64_t re, im;
             std::memcpy(&re, &v.x, 8);
             std::memcpy(&im, &v.y, 8);
@@ -611,38 +641,37 @@ static te_status try_pack(te_hamiltonian h, hipStream_t s, bool* packed) {
                 if (im != 0 || diag_row == r) return TE_OK;
                 diag_row = r;
                 diag[(size_t)r] = v.x;
-                code[(size_t)k] = kDiag;
+                pcode[(size_t)k] = vcode[(size_t)k] = kDiag;
                 continue;
             }
-            const int32_t off = c - r;
-            uint32_t q = (uint32_t)mix64(((uint64_t)(uint32_t)off << 32) ^ mix64(re) ^ (mix64(im) * 3u)) & (kPairSlots - 1);
-            while (slot[q] >= 0 && !(keys[q].off == off && keys[q].re == re && keys[q].im == im))
-                q = (q + 1) & (kPairSlots - 1);
-            if (slot[q] < 0) {
-                if ((int)toff.size() == kMaxPairs) return TE_OK;
-                slot[q] = (int32_t)toff.size();
-                keys[q] = PairKey{off, re, im};
-                toff.push_back(off);
-                tval.push_back(v);
-            }
-            code[(size_t)k] = (uint16_t)slot[q];
+            const int pq = pairs.code(c - r, re, im, v);
+            const int vq = values.code(0, re, im, v);
+            if (pq < 0 && vq < 0) return TE_OK;
+            pcode[(size_t)k] = (uint16_t)std::max(pq, 0);
+            vcode[(size_t)k] = (uint16_t)std::max(vq, 0);
         }
     }
-    const int dcode = (int)toff.size();  // the diagonal's code follows the pairs
-    toff.push_back(0);
-    tval.push_back(make_double2(0.0, 0.0));
+    const bool by_pairs = !pairs.full;
+    CodeTable& tab = by_pairs ? pairs : values;
+    std::vector<uint16_t>& code = by_pairs ? pcode : vcode;
+    const int dcode = (int)tab.off.size();  // the diagonal's code follows the table's
+    tab.off.push_back(0);
+    tab.val.push_back(make_double2(0.0, 0.0));
     const bool narrow = dcode <= 255;
     const size_t cbytes = (size_t)nnz * (narrow ? 1 : 2);
     // padded (zero bytes): a batch of 1-byte codes is read as whole dwords and may run past the end
     void* d_code = dev_alloc(cbytes + kCodePad);
-    int* d_toff = (int*)dev_alloc(toff.size() * sizeof(int));
-    double2* d_tval = (double2*)dev_alloc(tval.size() * sizeof(double2));
+    int* d_toff = (int*)dev_alloc(tab.off.size() * sizeof(int));
+    double2* d_tval = (double2*)dev_alloc(tab.val.size() * sizeof(double2));
     double* d_diag = (double*)dev_alloc((size_t)dim * sizeof(double));
-    if (!d_code || !d_toff || !d_tval || !d_diag) {
+    auto release = [&]() {
         dev_free(d_code);
         dev_free(d_toff);
         dev_free(d_tval);
         dev_free(d_diag);
+    };
+    if (!d_code || !d_toff || !d_tval || !d_diag) {
+        release();
         return TE_OK;  // no device memory for the packed copy: keep CSR
     }
     std::vector<uint8_t> code8;
@@ -653,22 +682,17 @@ static te_status try_pack(te_hamiltonian h, hipStream_t s, bool* packed) {
         for (int64_t k = 0; k < nnz; ++k)
             if (code[(size_t)k] == kDiag) code[(size_t)k] = (uint16_t)dcode;
     }
-    te_status rc = TE_OK;
     hipError_t e = hipMemsetAsync((char*)d_code + cbytes, 0, kCodePad, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(d_code, narrow ? (const void*)code8.data() : (const void*)code.data(), cbytes,
                            hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(d_toff, toff.data(), toff.size() * sizeof(int), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(d_tval, tval.data(), tval.size() * sizeof(double2), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_toff, tab.off.data(), tab.off.size() * sizeof(int), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_tval, tab.val.data(), tab.val.size() * sizeof(double2), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(d_diag, diag.data(), (size_t)dim * sizeof(double), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
-        rc = fail(TE_ERR_DEVICE, std::string("packing the entries: ") + hipGetErrorString(e));
-        dev_free(d_code);
-        dev_free(d_toff);
-        dev_free(d_tval);
-        dev_free(d_diag);
-        return rc;
+        release();
+        return fail(TE_ERR_DEVICE, std::string("packing the entries: ") + hipGetErrorString(e));
     }
     h->code = d_code;
     h->toff = d_toff;
@@ -677,17 +701,23 @@ static te_status try_pack(te_hamiltonian h, hipStream_t s, bool* packed) {
     Packed pk;
     if (narrow) pk.c8 = (const uint8_t*)d_code;
     else pk.c16 = (const uint16_t*)d_code;
+    pk.col = by_pairs ? nullptr : h->col;  // value codes keep the columns
     pk.toff = d_toff;
     pk.tval = d_tval;
     pk.diag = d_diag;
     pk.dcode = dcode;
     h->csr.pk = pk;
-    dev_free(h->col);
+    if (by_pairs) {
+        dev_free(h->col);
+        h->col = nullptr;
+        h->csr.col = nullptr;
+    }
     dev_free(h->val);
-    h->col = nullptr;
+    dev_free(h->rval);
     h->val = nullptr;
-    h->csr.col = nullptr;
+    h->rval = nullptr;
     h->csr.val = nullptr;
+    h->csr.rval = nullptr;
     *packed = true;
     return TE_OK;
 }
@@ -761,10 +791,25 @@ te_status te_hamiltonian_real_values(te_hamiltonian h, int32_t* real_values) {
 
 te_status te_hamiltonian_storage(te_hamiltonian h, int32_t* kind) {
     if (!h || !kind) return fail(TE_ERR_INVALID_ARG, "null pointer");
-    *kind = h->csr.pk.c8 ? TE_STORAGE_PACKED8 : h->csr.pk.c16 ? TE_STORAGE_PACKED16
-                                              : h->csr.rval   ? TE_STORAGE_REAL
-                                                              : TE_STORAGE_COMPLEX;
+    const Packed& pk = h->csr.pk;
+    if (pk.c8) *kind = pk.col ? TE_STORAGE_CODED8 : TE_STORAGE_PACKED8;
+    else if (pk.c16) *kind = pk.col ? TE_STORAGE_CODED16 : TE_STORAGE_PACKED16;
+    else *kind = h->csr.rval ? TE_STORAGE_REAL : TE_STORAGE_COMPLEX;
     return TE_OK;
+}
+
+te_status te_hamiltonian_pack(te_hamiltonian h, int32_t* kind, void* stream) {
+    if (!h) return fail(TE_ERR_INVALID_ARG, "null handle");
+    {
+        std::lock_guard<std::mutex> lock(h->mu);
+        if (!is_packed(h->csr.pk)) {
+            bool packed = false;
+            const te_status rc = try_pack(h, (hipStream_t)stream, &packed);
+            if (rc != TE_OK) return rc;
+            if (packed) h->tuned = false;  // the best shape depends on the storage
+        }
+    }
+    return kind ? te_hamiltonian_storage(h, kind) : TE_OK;
 }
 
 te_status te_hamiltonian_copy_csr(te_hamiltonian h, int32_t* row_ptr, int32_t* col_idx, te_c128* values,

@@ -206,9 +206,11 @@ struct CsrSrc {
     }
 };
 
-template <typename CT>
+// COLS: value codes with explicit columns (cols[k]); else codes of (column offset, value) pairs
+template <typename CT, bool COLS>
 struct PackSrc {
     const CT* __restrict__ code;
+    const int* __restrict__ cols;
     const int* __restrict__ toff;
     const double2* __restrict__ tval;
     const double* __restrict__ diag;
@@ -224,7 +226,8 @@ struct PackSrc {
     }
     __device__ __forceinline__ void load(int k, int& c, double2& v) const {
         const int q = code[k];
-        c = r + toff[q];
+        if constexpr (COLS) c = cols[k];
+        else c = r + toff[q];
         const double2 t = tval[q];
         v = (q == dcode) ? make_double2(dg, 0.0) : t;
     }
@@ -234,8 +237,10 @@ struct PackSrc {
 template <typename F>
 __device__ __forceinline__ void with_entries(const int* ci, const double2* val, const double* rval, const Packed& pk,
                                              F&& f) {
-    if (pk.c8) f(PackSrc<uint8_t>{pk.c8, pk.toff, pk.tval, pk.diag, pk.dcode});
-    else if (pk.c16) f(PackSrc<uint16_t>{pk.c16, pk.toff, pk.tval, pk.diag, pk.dcode});
+    if (pk.c8 && pk.col) f(PackSrc<uint8_t, true>{pk.c8, pk.col, pk.toff, pk.tval, pk.diag, pk.dcode});
+    else if (pk.c8) f(PackSrc<uint8_t, false>{pk.c8, nullptr, pk.toff, pk.tval, pk.diag, pk.dcode});
+    else if (pk.c16 && pk.col) f(PackSrc<uint16_t, true>{pk.c16, pk.col, pk.toff, pk.tval, pk.diag, pk.dcode});
+    else if (pk.c16) f(PackSrc<uint16_t, false>{pk.c16, nullptr, pk.toff, pk.tval, pk.diag, pk.dcode});
     else if (rval) f(CsrSrc<double>{ci, rval});
     else f(CsrSrc<double2>{ci, val});
 }
@@ -347,10 +352,14 @@ __device__ __forceinline__ void tile_spmv(const int* __restrict__ rp, const int*
             s_tval[i] = pk.tval[i];
         }
         __syncthreads();
-        if constexpr (G == 1 && U % 4 == 0)
+        if (pk.col)
+            tile_spmv_t<G, U>(rp, PackSrc<uint8_t, true>{pk.c8, pk.col, s_toff, s_tval, pk.diag, pk.dcode}, x, r0, r1,
+                              y, ytile);
+        else if constexpr (G == 1 && U % 4 == 0)
             tile_spmv_p8_rows<U, 1>(rp, pk.c8, s_toff, s_tval, pk.diag, pk.dcode, x, r0, r1, y, ytile);
         else
-            tile_spmv_t<G, U>(rp, PackSrc<uint8_t>{pk.c8, s_toff, s_tval, pk.diag, pk.dcode}, x, r0, r1, y, ytile);
+            tile_spmv_t<G, U>(rp, PackSrc<uint8_t, false>{pk.c8, nullptr, s_toff, s_tval, pk.diag, pk.dcode}, x, r0,
+                              r1, y, ytile);
         return;
     }
     with_entries(ci, val, rval, pk, [&](const auto& src) { tile_spmv_t<G, U>(rp, src, x, r0, r1, y, ytile); });

@@ -85,10 +85,12 @@ struct RedBuf {
 // Packed entries: entry k of row r holds a code q; q stands for column r + toff[q] and value
 // tval[q], except q = dcode, the row's diagonal: column r, value (diag[r], 0).  Codes are one
 // byte when there are at most 255 distinct (column offset, value) pairs off the diagonal, else
-// two bytes.
+// two bytes.  Value codes: when the pairs are too many but the values few, col keeps every
+// entry's column and the codes index values only (toff is then all zero).
 struct Packed {
     const uint8_t* c8 = nullptr;    // 1-byte codes, or
     const uint16_t* c16 = nullptr;  // 2-byte codes (at most one is set)
+    const int* col = nullptr;       // value codes: the columns; else unset
     const int* toff = nullptr;      // [dcode + 1] column offsets, toff[dcode] = 0
     const double2* tval = nullptr;  // [dcode + 1] values
     const double* diag = nullptr;   // [dim] real diagonal (0 where a row has none)
@@ -241,11 +243,13 @@ struct Csr {
 inline bool is_packed(const Packed& p) { return p.c8 != nullptr || p.c16 != nullptr; }
 
 // bytes a sparse product streams for the stored entries (row pointers and vectors aside):
-// value + column index per entry, or a code per entry and the real diagonal per row
+// value + column index per entry, or a code (and with value codes a column) per entry and the
+// real diagonal per row
 inline double csr_entries_bytes(const Csr& c) {
     const double nnz = (double)c.nnz, d = (double)c.dim;
-    if (c.pk.c8) return 1.0 * nnz + 8.0 * d;
-    if (c.pk.c16) return 2.0 * nnz + 8.0 * d;
+    const double cols = c.pk.col ? 4.0 * nnz : 0.0;
+    if (c.pk.c8) return 1.0 * nnz + cols + 8.0 * d;
+    if (c.pk.c16) return 2.0 * nnz + cols + 8.0 * d;
     return (c.rval ? 12.0 : 20.0) * nnz;
 }
 

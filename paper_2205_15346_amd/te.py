@@ -31,7 +31,8 @@ TE_CHECK_HERMITIAN = 2
 TE_STORE_COMPLEX = 4
 TE_STORE_CSR = 8
 TE_STORAGE_COMPLEX, TE_STORAGE_REAL, TE_STORAGE_PACKED8, TE_STORAGE_PACKED16 = 0, 1, 2, 3
-STORAGE_NAMES = {0: "complex", 1: "real", 2: "packed8", 3: "packed16"}
+TE_STORAGE_CODED8, TE_STORAGE_CODED16 = 4, 5
+STORAGE_NAMES = {0: "complex", 1: "real", 2: "packed8", 3: "packed16", 4: "coded8", 5: "coded16"}
 TE_MAX_KRYLOV = 64
 
 
@@ -154,6 +155,7 @@ _SIGS = {
     "te_hamiltonian_info": (_I, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), _PD]),
     "te_hamiltonian_real_values": (_I, [_P, _PI]),
     "te_hamiltonian_storage": (_I, [_P, _PI]),
+    "te_hamiltonian_pack": (_I, [_P, _PI, _P]),
     "te_hamiltonian_copy_csr": (_I, [_P, _P, _P, _P, ctypes.c_uint32, _P]),
     "te_memory_burden_defaults": (None, [ctypes.c_void_p]),
     "te_hamiltonian_create_memory_burden": (_I, [ctypes.POINTER(_P), ctypes.c_void_p, ctypes.POINTER(_I64), _P]),
@@ -252,7 +254,7 @@ class Hamiltonian:
         self.real_values = bool(rv.value)  # entries stored as real (8 B) rather than complex
         sk = ctypes.c_int32()
         _check(_lib.te_hamiltonian_storage(self._h, ctypes.byref(sk)))
-        self.storage = STORAGE_NAMES[sk.value]  # "complex", "real", "packed8" or "packed16"
+        self.storage = STORAGE_NAMES[sk.value]  # "complex", "real", "packed8/16" or "coded8/16"
 
     @property
     def handle(self):
@@ -339,6 +341,15 @@ def te_hamiltonian_create_bose_chain(U, hop, N: int, store_complex=False, stream
                                                  ctypes.c_void_p(a.ctypes.data) if a.size else None, flags,
                                                  _stream(stream)))
     return Hamiltonian(h)
+
+
+def te_hamiltonian_pack(H: Hamiltonian, stream=None) -> str:
+    """Packs a CSR handle's entries in place (as creation would); returns the storage name."""
+    k = ctypes.c_int32()
+    _check(_lib.te_hamiltonian_pack(H.handle, ctypes.byref(k), _stream(stream)))
+    H.storage = STORAGE_NAMES[k.value]
+    H.real_values = H.storage == "real"
+    return H.storage
 
 
 def te_hamiltonian_copy_csr(H: Hamiltonian, stream=None):

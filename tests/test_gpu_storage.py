@@ -5,7 +5,8 @@ computes the same products in the same order, so every result is compared bitwis
 kinds, and against the oracle.  Matrices: the phase-twisted XXZ ring (complex, 2 pairs per
 bond: 1-byte codes), its real part (real symmetric), the paper's own model (real), the Bose
 chain (complex, hundreds of pairs: 2-byte codes), random Hermitian matrices (2-byte codes, or
-too many pairs to pack)."""
+too many pairs to pack), random patterns with few values (too many pairs, value codes beside
+the columns), the paper's model built on the device and packed afterwards."""
 
 import numpy as np
 import pytest
@@ -22,6 +23,22 @@ pytestmark = pytest.mark.gpu
 def real_xxz(L, seed, n_v0=1):
     H, v = W.xxz_chain(L, seed, n_v0=n_v0)
     return CSR(H.dim, H.row_ptr, H.col, np.ascontiguousarray(H.val.real.astype(np.complex128)), H.name + "_re"), v
+
+
+def few_values_hermitian(d, density, seed, n_values):
+    """A random Hermitian pattern whose entries take n_values values (and their conjugates): too
+    many (column - row, value) pairs to pack, few values."""
+    R = random_hermitian_csr(d, density, seed)
+    rng = np.random.default_rng(seed + 1)
+    table = rng.standard_normal(n_values) + 1j * rng.standard_normal(n_values)
+    rows = np.repeat(np.arange(d), np.diff(R.row_ptr)).astype(np.int64)
+    col = R.col.astype(np.int64)
+    lo, hi = np.minimum(rows, col), np.maximum(rows, col)
+    mixed = ((lo.astype(np.uint64) * np.uint64(0x9E3779B1) + hi.astype(np.uint64)) * np.uint64(0x85EBCA6B)) >> np.uint64(13)
+    v = table[(mixed % np.uint64(n_values)).astype(np.int64)]
+    v = np.where(rows < col, v, np.conj(v))
+    v = np.where(rows == col, v.real + 0j, v)
+    return CSR(d, R.row_ptr, R.col, np.ascontiguousarray(v), f"few_values_{n_values}")
 
 
 def kinds(H):
@@ -62,10 +79,16 @@ def test_storage_detection():
     R = random_hermitian_csr(300, 0.03, seed=2)
     hr = te.te_hamiltonian_create(R.row_ptr, R.col, R.val)
     assert hr.storage == "packed16" and roundtrip(te, hr, R)
-    # more than 65535 distinct pairs: CSR
+    # more than 65535 distinct pairs and values: CSR
     Rb = random_hermitian_csr(3000, 0.01, seed=3)
     hrb = te.te_hamiltonian_create(Rb.row_ptr, Rb.col, Rb.val)
     assert hrb.storage == "complex" and roundtrip(te, hrb, Rb)
+    # more than 65535 pairs, few values: value codes beside the columns
+    for n_values, kind in ((40, "coded8"), (2000, "coded16")):
+        F = few_values_hermitian(3000, 0.01, 5, n_values)
+        hf = te.te_hamiltonian_create(F.row_ptr, F.col, F.val, check_hermitian=True)
+        assert hf.storage == kind and roundtrip(te, hf, F)
+        hf.destroy()
     # one tiny imaginary pair: still packed, values kept bit for bit
     val = H.val.copy()
     rows = np.repeat(np.arange(H.dim), np.diff(H.row_ptr))
@@ -138,6 +161,54 @@ def test_evolve_is_bitwise_across_storage(shape, real):
     destroy(*hs)
 
 
+@pytest.mark.parametrize("n_values", [40, 2000])
+@pytest.mark.parametrize("shape", [(4, 4, 2, 2, 1), (1, 8, 4, 2, 1), (8, 2, 1, 1, 0), (1, 16, 2, 2, 0)])
+def test_value_codes_evolve_bitwise_and_match_oracle(shape, n_values):
+    announce(f"value codes ({n_values} values), shape {shape}")
+    te = lib()
+    H = few_values_hermitian(3000, 0.01, 5, n_values)
+    v0 = W.random_state(np.random.default_rng(6), H.dim)
+    hs = kinds(H)
+    assert [h.storage for h in hs] == ["coded8" if n_values < 128 else "coded16", "complex", "complex"]
+    x = to_dev(v0)
+    out = []
+    for h in hs[:2]:
+        te.te_set_tuning(h, *shape)
+        v, res = te.te_evolve(h, x, 1.5, 1e-8, 30)
+        out.append((to_host(v), res.steps, res.err_bound))
+    assert np.array_equal(out[0][0], out[1][0]) and out[0][1:] == out[1][1:]
+    ro = O.evolve(H, v0, 1.5, 1e-8, 30)
+    assert np.linalg.norm(out[0][0] - ro.v) <= 2e-8 + 1e-12
+    destroy(*hs)
+
+
+def test_packing_a_device_built_matrix():
+    """te_hamiltonian_pack on the paper's model built on the device (real CSR): at the Fig. 1
+    size its pairs pack; with 20 memory qubits and 5 excitations they are too many and its
+    couplings become value codes.  Evolutions are bitwise those of the unpacked handle."""
+    announce("packing device-built matrices")
+    te = lib()
+    for params, kind in ((dict(), "packed8"), (dict(K=10, Kp=10, N0=10, Nm=5), "coded8")):
+        h, idx = te.te_hamiltonian_create_memory_burden(**params)
+        hc, _ = te.te_hamiltonian_create_memory_burden(**params)
+        assert h.storage == "real"
+        rp0, ci0, va0 = te.te_hamiltonian_copy_csr(h)
+        assert te.te_hamiltonian_pack(h) == kind and h.storage == kind
+        assert te.te_hamiltonian_pack(h) == kind  # no-op when packed
+        rp1, ci1, va1 = te.te_hamiltonian_copy_csr(h)
+        assert np.array_equal(rp0, rp1) and np.array_equal(ci0, ci1) and np.array_equal(va0, va1)
+        v0 = np.zeros(h.dim, dtype=np.complex128)
+        v0[idx] = 1.0
+        x = to_dev(v0)
+        out = []
+        for hh in (h, hc):
+            te.te_set_tuning(hh, 4, 4, 2, 2, 1)
+            v, res = te.te_evolve(hh, x, 2.0, 1e-8, 40)
+            out.append((to_host(v), res.steps, res.err_bound))
+        assert np.array_equal(out[0][0], out[1][0]) and out[0][1:] == out[1][1:]
+        destroy(h, hc)
+
+
 @pytest.mark.parametrize("shape", [(4, 4, 2, 2, 1), (1, 8, 4, 2, 1), (2, 8, 2, 2, 0)])
 def test_two_byte_codes_evolve_bitwise_and_match_oracle(shape):
     announce(f"2-byte codes: Bose chain, shape {shape}")
@@ -198,10 +269,10 @@ def test_batch_mixes_storage_kinds():
     te = lib()
     H, vs = real_xxz(11, seed=9, n_v0=3)
     hp, hr, hc = kinds(H)
-    R = random_hermitian_csr(900, 0.02, seed=10)
+    R = few_values_hermitian(3000, 0.01, 10, 40)
     hz = te.te_hamiltonian_create(R.row_ptr, R.col, R.val)
-    assert hz.storage == "packed16"
-    rv = [W.random_state(np.random.default_rng(11), 900)]
+    assert hz.storage == "coded8"
+    rv = [W.random_state(np.random.default_rng(11), 3000)]
     groups = [(hp, [to_dev(v) for v in vs], 6.0, 1e-8), (hr, [to_dev(v) for v in vs], 6.0, 1e-8),
               (hc, [to_dev(v) for v in vs], 6.0, 1e-8), (hp, [to_dev(vs[0])], 4.0, 1e-8),
               (hz, [to_dev(v) for v in rv], 3.0, 1e-8)]
