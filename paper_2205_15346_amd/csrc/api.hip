@@ -803,10 +803,16 @@ te_status te_hamiltonian_pack(te_hamiltonian h, int32_t* kind, void* stream) {
     {
         std::lock_guard<std::mutex> lock(h->mu);
         if (!is_packed(h->csr.pk)) {
+            TE_HIP(hipDeviceSynchronize());  // no work in flight may still read the arrays freed below
             bool packed = false;
             const te_status rc = try_pack(h, (hipStream_t)stream, &packed);
             if (rc != TE_OK) return rc;
-            if (packed) h->tuned = false;  // the best shape depends on the storage
+            if (packed) {
+                // the workspace's restart graph holds the CSR arrays: drop it with the workspace
+                delete h->ws;
+                h->ws = nullptr;
+                h->tuned = false;  // the best shape depends on the storage
+            }
         }
     }
     return kind ? te_hamiltonian_storage(h, kind) : TE_OK;
@@ -1366,7 +1372,8 @@ te_status te_set_tuning(te_hamiltonian h, const te_tuning* t) {
     if (!h || !t) return fail(TE_ERR_INVALID_ARG, "null pointer");
     if (!tiling_supported(t->rows_per_thread, t->lanes_per_row, t->nnz_per_lane, t->update_rows_per_thread,
                           t->split_projection))
-        return fail(TE_ERR_INVALID_ARG, "unsupported tuning (lanes 4 with 1 or 4 nonzeros, lanes 8 with 2; rows 1 or 2)");
+        return fail(TE_ERR_INVALID_ARG, "unsupported tuning (lanes x nonzeros 4x1, 4x4, 8x2, 2x8, 1x8 or 1x16; "
+                                        "rows per thread 1, 2 or 4; update rows 1 or 2; split 0 or 1)");
     std::lock_guard<std::mutex> lock(h->mu);
     h->tuning = *t;
     h->tuned = true;
