@@ -574,8 +574,26 @@ __global__ __launch_bounds__(kBlock) void k_gspmm(const JobView* __restrict__ jo
     const unsigned mask = group_mask<NV>(jobs, gv, j, xs, ys);
     if (mask == 0) return;
     const int r0 = it.y * kBlock;
-    with_entries(gv.ci, gv.val, gv.rval, gv.pk, [&](const auto& src) {
-        group_spmv<G, U, NV>(gv, src, r0, min(r0 + kBlock, gv.dim), mask, xs, ys, nullptr);
+    const int r1 = min(r0 + kBlock, gv.dim);
+    const Packed& pk = gv.pk;
+    if (pk.c8) {  // the 1-byte code table staged in LDS, as for the single-vector product
+        __shared__ int s_toff[256];
+        __shared__ double2 s_tval[256];
+        for (int i = threadIdx.x; i <= pk.dcode; i += kBlock) {
+            s_toff[i] = pk.toff[i];
+            s_tval[i] = pk.tval[i];
+        }
+        __syncthreads();
+        if (pk.col)
+            group_spmv<G, U, NV>(gv, PackSrc<uint8_t, true>{pk.c8, pk.col, s_toff, s_tval, pk.diag, pk.dcode}, r0,
+                                 r1, mask, xs, ys, nullptr);
+        else
+            group_spmv<G, U, NV>(gv, PackSrc<uint8_t, false>{pk.c8, nullptr, s_toff, s_tval, pk.diag, pk.dcode}, r0,
+                                 r1, mask, xs, ys, nullptr);
+        return;
+    }
+    with_entries(gv.ci, gv.val, gv.rval, pk, [&](const auto& src) {
+        group_spmv<G, U, NV>(gv, src, r0, r1, mask, xs, ys, nullptr);
     });
 }
 
