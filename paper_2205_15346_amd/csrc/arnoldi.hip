@@ -290,7 +290,8 @@ __device__ __forceinline__ void tile_spmv_t(const int* __restrict__ rp, const Sr
 // One row per thread, 1-byte codes.  The U * H codes of a batch come from U * H / 4 + 1 aligned
 // dword loads (the code array is padded so that the last batch's over-read stays inside it),
 // byte-aligned with v_alignbyte; their gathers follow in H groups of U.  A row of up to U * H
-// entries thus costs one round trip for its codes and the gathers behind it.
+// entries thus costs one round trip for its codes and the gathers behind it.  Entries past the
+// row's end gather x[r] (in bounds, unused), so a group's gathers carry no branches.
 template <int U, int H>
 __device__ __forceinline__ void tile_spmv_p8_rows(const int* __restrict__ rp, const uint8_t* __restrict__ code,
                                                   const int* toff, const double2* tval,
@@ -319,18 +320,17 @@ __device__ __forceinline__ void tile_spmv_p8_rows(const int* __restrict__ rp, co
                 for (int q = 0; q < U; ++q) {
                     const int e = h * U + q;
                     const int c8 = (int)((b[e >> 2] >> (8 * (e & 3))) & 0xffu);
-                    if (k0 + e < ke) {
-                        cc[q] = r + toff[c8];
-                        const double2 t = tval[c8];
-                        vv[q] = (c8 == dcode) ? make_double2(dg, 0.0) : t;
-                    } else {
-                        cc[q] = -1;
-                        vv[q] = make_double2(0.0, 0.0);
-                    }
+                    const bool live = k0 + e < ke;
+                    cc[q] = live ? r + toff[c8] : r;
+                    const double2 t = tval[live ? c8 : dcode];
+                    vv[q] = (c8 == dcode) ? make_double2(dg, 0.0) : t;
                 }
+                double2 xv[U];
+#pragma unroll
+                for (int q = 0; q < U; ++q) xv[q] = x[cc[q]];
 #pragma unroll
                 for (int q = 0; q < U; ++q)
-                    if (cc[q] >= 0) acc = entry_fma(vv[q], x[cc[q]], acc);
+                    if (k0 + h * U + q < ke) acc = entry_fma(vv[q], xv[q], acc);
             }
         }
         y[r] = acc;
