@@ -186,7 +186,8 @@ te_status te_hamiltonian_storage(te_hamiltonian h, int32_t* kind);
 te_status te_hamiltonian_pack(te_hamiltonian h, int32_t* kind, void* stream);
 
 /* Copies the handle's CSR out: row_ptr[dim+1], col_idx[nnz], values[nnz] (complex; real
- * entries are returned with zero imaginary parts).  Device pointers with TE_PTR_DEVICE, else
+ * entries are returned with zero imaginary parts; packed entries are expanded back, bit for
+ * bit, in their stored order; the expansion takes nnz * 20 bytes of device scratch).  Device pointers with TE_PTR_DEVICE, else
  * host.  Any of the three may be NULL (not copied).  Synchronous. */
 te_status te_hamiltonian_copy_csr(te_hamiltonian h, int32_t* row_ptr, int32_t* col_idx, te_c128* values,
                                   uint32_t flags, void* stream);
