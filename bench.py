@@ -370,6 +370,8 @@ def main():
                     help="projection kernel shape lanes,nnz,rows,update_rows,split for the single solve "
                          "(default: the shape te_autotune selects for this matrix on MI355X), or 'auto'")
     ap.add_argument("--three-term", type=int, default=1, help="also time the three-term mode (0: skip)")
+    ap.add_argument("--csr-storage", type=int, default=1,
+                    help="also time the solve with the matrix kept as CSR instead of packed (0: skip)")
     ap.add_argument("--batch-instances", type=int, default=256, help="instances of the XXZ batch (0: skip)")
     ap.add_argument("--batch-profile", type=int, default=1, help="also run the batch in profiling mode")
     ap.add_argument("--serve-requests", type=int, default=16, help="requests of the serving run (0: skip)")
@@ -440,6 +442,24 @@ def main():
 
     # ---- three-term mode (TE_OPT_LANCZOS3; informational, not the headline)
     three_term = bench_three_term(te, torch, H, v0, out, wl, args.steps) if args.three_term else None
+
+    # ---- the same solves with the matrix kept as CSR (TE_STORE_CSR; informational)
+    csr = None
+    if args.csr_storage:
+        Hc = te.te_hamiltonian_create(wl.H.row_ptr, wl.H.col, wl.H.val, store_csr=True)
+        te.te_set_tuning(Hc, 8, 2, 4, 2, 1)  # the fastest whole-solve shape on the CSR (measured)
+        te.te_evolve(Hc, v0, wl.t, wl.tol, wl.m, options=plain, out=out)  # warm-up
+        torch.cuda.synchronize()
+        c0 = time.perf_counter()
+        for i in range(args.steps):
+            _, rc = te.te_evolve(Hc, v0, wl.t, wl.tol, wl.m, options=plain, out=out)
+        torch.cuda.synchronize()
+        csr_elapsed = time.perf_counter() - c0
+        csr = {"storage": Hc.storage, "ms_per_step": 1e3 * csr_elapsed / args.steps,
+               "value": args.steps / csr_elapsed, "restarts_per_solve": rc.steps,
+               "kernel_shape": te.te_get_tuning(Hc).as_dict()}
+        Hc.destroy()
+        log(f"[bench] CSR storage ({csr['storage']}): {csr['ms_per_step']:.1f} ms per solve")
 
     kernel_gbs = {k: (v["bytes"] / v["seconds"] / 1e9 if v["seconds"] > 0 else None) for k, v in totals.items()}
     traffic = measured_traffic(os.path.join(ROOT, "paper_2205_15346_amd", "csrc", "arnoldi.hip"))
@@ -512,6 +532,7 @@ def main():
         "matvecs_per_solve": matvecs,
         "err_bound": bound,
         "graph_mode": {"ms_per_step": 1e3 * graph_elapsed / args.steps, "value": args.steps / graph_elapsed},
+        "csr_storage": csr,
         "kernel_shape": tuning,
         "three_term_mode": three_term,
         "batch": batch,
