@@ -133,6 +133,7 @@ te_hamiltonian_s::~te_hamiltonian_s() {
     dev_free(val);
     dev_free(rval);
     dev_free(code);
+    dev_free(slice);
     dev_free(toff);
     dev_free(tval);
     dev_free(diag);
@@ -657,30 +658,68 @@ static te_status try_pack(te_hamiltonian h, hipStream_t s, bool* packed) {
     const int dcode = (int)tab.off.size();  // the diagonal's code follows the table's
     tab.off.push_back(0);
     tab.val.push_back(make_double2(0.0, 0.0));
+    for (auto& q : code)
+        if (q == kDiag) q = (uint16_t)dcode;
+    // value codes: codes and columns sliced in chunks of 64 rows (te::Packed)
+    const int nch = (dim + 63) / 64;
+    std::vector<int> slice, scol;
+    if (!by_pairs) {
+        std::vector<int> cols;
+        std::vector<uint16_t> scode;
+        int64_t total = 0;
+        try {
+            slice.resize((size_t)nch);
+            for (int c = 0; c < nch; ++c) {
+                int w = 0;
+                for (int rr = 64 * c; rr < std::min(dim, 64 * c + 64); ++rr) w = std::max(w, rp[(size_t)rr + 1] - rp[(size_t)rr]);
+                slice[(size_t)c] = (int)total;
+                total += 64 * (int64_t)w;
+                if (total >= ((int64_t)1 << 31)) return TE_OK;  // positions would not fit int32: keep CSR
+            }
+            cols.resize((size_t)nnz);
+            scol.assign((size_t)total, 0);
+            scode.assign((size_t)total, 0);
+        } catch (...) {
+            return TE_OK;
+        }
+        TE_HIP(hipMemcpyAsync(cols.data(), h->csr.col, (size_t)nnz * sizeof(int), hipMemcpyDeviceToHost, s));
+        TE_HIP(hipStreamSynchronize(s));
+        for (int rr = 0; rr < dim; ++rr) {
+            const int64_t at = slice[(size_t)(rr >> 6)] + (rr & 63);
+            for (int k = rp[(size_t)rr]; k < rp[(size_t)rr + 1]; ++k) {
+                const int64_t i = at + 64 * (int64_t)(k - rp[(size_t)rr]);
+                scol[(size_t)i] = cols[(size_t)k];
+                scode[(size_t)i] = code[(size_t)k];
+            }
+        }
+        code.swap(scode);
+    }
+    const int64_t ncode = (int64_t)code.size();
     const bool narrow = dcode <= 255;
-    const size_t cbytes = (size_t)nnz * (narrow ? 1 : 2);
+    const size_t cbytes = (size_t)ncode * (narrow ? 1 : 2);
     // padded (zero bytes): a batch of 1-byte codes is read as whole dwords and may run past the end
     void* d_code = dev_alloc(cbytes + kCodePad);
     int* d_toff = (int*)dev_alloc(tab.off.size() * sizeof(int));
     double2* d_tval = (double2*)dev_alloc(tab.val.size() * sizeof(double2));
     double* d_diag = (double*)dev_alloc((size_t)dim * sizeof(double));
+    int* d_scol = by_pairs ? nullptr : (int*)dev_alloc(scol.size() * sizeof(int));
+    int* d_slice = by_pairs ? nullptr : (int*)dev_alloc(slice.size() * sizeof(int));
     auto release = [&]() {
         dev_free(d_code);
         dev_free(d_toff);
         dev_free(d_tval);
         dev_free(d_diag);
+        dev_free(d_scol);
+        dev_free(d_slice);
     };
-    if (!d_code || !d_toff || !d_tval || !d_diag) {
+    if (!d_code || !d_toff || !d_tval || !d_diag || (!by_pairs && (!d_scol || !d_slice))) {
         release();
         return TE_OK;  // no device memory for the packed copy: keep CSR
     }
     std::vector<uint8_t> code8;
     if (narrow) {
-        code8.resize((size_t)nnz);
-        for (int64_t k = 0; k < nnz; ++k) code8[(size_t)k] = code[(size_t)k] == kDiag ? (uint8_t)dcode : (uint8_t)code[(size_t)k];
-    } else {
-        for (int64_t k = 0; k < nnz; ++k)
-            if (code[(size_t)k] == kDiag) code[(size_t)k] = (uint16_t)dcode;
+        code8.resize((size_t)ncode);
+        for (int64_t k = 0; k < ncode; ++k) code8[(size_t)k] = (uint8_t)code[(size_t)k];
     }
     hipError_t e = hipMemsetAsync((char*)d_code + cbytes, 0, kCodePad, s);
     if (e == hipSuccess)
@@ -689,6 +728,10 @@ static te_status try_pack(te_hamiltonian h, hipStream_t s, bool* packed) {
     if (e == hipSuccess) e = hipMemcpyAsync(d_toff, tab.off.data(), tab.off.size() * sizeof(int), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(d_tval, tab.val.data(), tab.val.size() * sizeof(double2), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(d_diag, diag.data(), (size_t)dim * sizeof(double), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !by_pairs)
+        e = hipMemcpyAsync(d_scol, scol.data(), scol.size() * sizeof(int), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !by_pairs)
+        e = hipMemcpyAsync(d_slice, slice.data(), slice.size() * sizeof(int), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         release();
@@ -698,20 +741,20 @@ static te_status try_pack(te_hamiltonian h, hipStream_t s, bool* packed) {
     h->toff = d_toff;
     h->tval = d_tval;
     h->diag = d_diag;
+    h->slice = d_slice;
     Packed pk;
     if (narrow) pk.c8 = (const uint8_t*)d_code;
     else pk.c16 = (const uint16_t*)d_code;
-    pk.col = by_pairs ? nullptr : h->col;  // value codes keep the columns
+    pk.col = d_scol;  // value codes: the sliced columns
+    pk.slice = d_slice;
     pk.toff = d_toff;
     pk.tval = d_tval;
     pk.diag = d_diag;
     pk.dcode = dcode;
     h->csr.pk = pk;
-    if (by_pairs) {
-        dev_free(h->col);
-        h->col = nullptr;
-        h->csr.col = nullptr;
-    }
+    dev_free(h->col);  // CSR columns: dropped (pairs) or replaced by the sliced copy
+    h->col = d_scol;
+    h->csr.col = nullptr;
     dev_free(h->val);
     dev_free(h->rval);
     h->val = nullptr;

@@ -199,35 +199,50 @@ struct CsrSrc {
     const int* __restrict__ ci;
     const VT* __restrict__ val;
     using V = VT;
-    __device__ __forceinline__ CsrSrc row(int) const { return *this; }
+    __device__ __forceinline__ CsrSrc row(int, int) const { return *this; }
     __device__ __forceinline__ void load(int k, int& c, VT& v) const {
         c = ci[k];
         v = val[k];
     }
 };
 
-// COLS: value codes with explicit columns (cols[k]); else codes of (column offset, value) pairs
+// COLS: value codes with explicit columns, both stored sliced (entry q of row r at
+// slice[r / 64] + 64 q + r % 64, so that the rows of a wave read consecutive addresses);
+// else codes of (column offset, value) pairs in CSR order.
 template <typename CT, bool COLS>
 struct PackSrc {
     const CT* __restrict__ code;
     const int* __restrict__ cols;
+    const int* __restrict__ slice;
     const int* __restrict__ toff;
     const double2* __restrict__ tval;
     const double* __restrict__ diag;
     int dcode;
     int r = 0;
+    int at = 0;  // sliced: position of the row's first entry (entry k at at + 64 (k - kb))
+    int kb = 0;
     double dg = 0.0;
     using V = double2;
-    __device__ __forceinline__ PackSrc row(int rr) const {
+    __device__ __forceinline__ PackSrc row(int rr, int kb_) const {
         PackSrc p = *this;
         p.r = rr;
         p.dg = diag[rr];
+        if constexpr (COLS) {
+            p.at = slice[rr >> 6] + (rr & 63);
+            p.kb = kb_;
+        }
         return p;
     }
     __device__ __forceinline__ void load(int k, int& c, double2& v) const {
-        const int q = code[k];
-        if constexpr (COLS) c = cols[k];
-        else c = r + toff[q];
+        int q;
+        if constexpr (COLS) {
+            const int i = at + 64 * (k - kb);
+            q = code[i];
+            c = cols[i];
+        } else {
+            q = code[k];
+            c = r + toff[q];
+        }
         const double2 t = tval[q];
         v = (q == dcode) ? make_double2(dg, 0.0) : t;
     }
@@ -237,10 +252,11 @@ struct PackSrc {
 template <typename F>
 __device__ __forceinline__ void with_entries(const int* ci, const double2* val, const double* rval, const Packed& pk,
                                              F&& f) {
-    if (pk.c8 && pk.col) f(PackSrc<uint8_t, true>{pk.c8, pk.col, pk.toff, pk.tval, pk.diag, pk.dcode});
-    else if (pk.c8) f(PackSrc<uint8_t, false>{pk.c8, nullptr, pk.toff, pk.tval, pk.diag, pk.dcode});
-    else if (pk.c16 && pk.col) f(PackSrc<uint16_t, true>{pk.c16, pk.col, pk.toff, pk.tval, pk.diag, pk.dcode});
-    else if (pk.c16) f(PackSrc<uint16_t, false>{pk.c16, nullptr, pk.toff, pk.tval, pk.diag, pk.dcode});
+    if (pk.c8 && pk.col) f(PackSrc<uint8_t, true>{pk.c8, pk.col, pk.slice, pk.toff, pk.tval, pk.diag, pk.dcode});
+    else if (pk.c8) f(PackSrc<uint8_t, false>{pk.c8, nullptr, nullptr, pk.toff, pk.tval, pk.diag, pk.dcode});
+    else if (pk.c16 && pk.col)
+        f(PackSrc<uint16_t, true>{pk.c16, pk.col, pk.slice, pk.toff, pk.tval, pk.diag, pk.dcode});
+    else if (pk.c16) f(PackSrc<uint16_t, false>{pk.c16, nullptr, nullptr, pk.toff, pk.tval, pk.diag, pk.dcode});
     else if (rval) f(CsrSrc<double>{ci, rval});
     else f(CsrSrc<double2>{ci, val});
 }
@@ -257,7 +273,7 @@ __device__ __forceinline__ void tile_spmv_t(const int* __restrict__ rp, const Sr
     for (int r = r0 + grp; r < r1; r += kBlock / G) {
         double2 acc = make_double2(0.0, 0.0);
         const int kb = rp[r], ke = rp[r + 1];
-        const Src rs = src.row(r);
+        const Src rs = src.row(r, kb);
         for (int k0 = kb + lg; k0 < ke; k0 += G * U) {
             VT vv[U];
             int cc[U];
@@ -353,13 +369,13 @@ __device__ __forceinline__ void tile_spmv(const int* __restrict__ rp, const int*
         }
         __syncthreads();
         if (pk.col)
-            tile_spmv_t<G, U>(rp, PackSrc<uint8_t, true>{pk.c8, pk.col, s_toff, s_tval, pk.diag, pk.dcode}, x, r0, r1,
-                              y, ytile);
+            tile_spmv_t<G, U>(rp, PackSrc<uint8_t, true>{pk.c8, pk.col, pk.slice, s_toff, s_tval, pk.diag, pk.dcode},
+                              x, r0, r1, y, ytile);
         else if constexpr (G == 1 && U % 4 == 0)
             tile_spmv_p8_rows<U, 1>(rp, pk.c8, s_toff, s_tval, pk.diag, pk.dcode, x, r0, r1, y, ytile);
         else
-            tile_spmv_t<G, U>(rp, PackSrc<uint8_t, false>{pk.c8, nullptr, s_toff, s_tval, pk.diag, pk.dcode}, x, r0,
-                              r1, y, ytile);
+            tile_spmv_t<G, U>(rp, PackSrc<uint8_t, false>{pk.c8, nullptr, nullptr, s_toff, s_tval, pk.diag, pk.dcode},
+                              x, r0, r1, y, ytile);
         return;
     }
     with_entries(ci, val, rval, pk, [&](const auto& src) { tile_spmv_t<G, U>(rp, src, x, r0, r1, y, ytile); });
@@ -515,7 +531,7 @@ __device__ __forceinline__ void group_spmv(const GroupView& gv, const Src& src, 
 #pragma unroll
         for (int v = 0; v < NV; ++v) acc[v] = make_double2(0.0, 0.0);
         const int kb = rp[r], ke = rp[r + 1];
-        const Src rs = src.row(r);
+        const Src rs = src.row(r, kb);
         for (int k0 = kb + lg; k0 < ke; k0 += G * U) {
             VT vv[U];
             int cc[U];
@@ -585,11 +601,12 @@ __global__ __launch_bounds__(kBlock) void k_gspmm(const JobView* __restrict__ jo
         }
         __syncthreads();
         if (pk.col)
-            group_spmv<G, U, NV>(gv, PackSrc<uint8_t, true>{pk.c8, pk.col, s_toff, s_tval, pk.diag, pk.dcode}, r0,
-                                 r1, mask, xs, ys, nullptr);
+            group_spmv<G, U, NV>(gv, PackSrc<uint8_t, true>{pk.c8, pk.col, pk.slice, s_toff, s_tval, pk.diag, pk.dcode},
+                                 r0, r1, mask, xs, ys, nullptr);
         else
-            group_spmv<G, U, NV>(gv, PackSrc<uint8_t, false>{pk.c8, nullptr, s_toff, s_tval, pk.diag, pk.dcode}, r0,
-                                 r1, mask, xs, ys, nullptr);
+            group_spmv<G, U, NV>(gv,
+                                 PackSrc<uint8_t, false>{pk.c8, nullptr, nullptr, s_toff, s_tval, pk.diag, pk.dcode},
+                                 r0, r1, mask, xs, ys, nullptr);
         return;
     }
     with_entries(gv.ci, gv.val, gv.rval, pk, [&](const auto& src) {
@@ -942,8 +959,9 @@ __device__ __forceinline__ double2 spmv_rows(const int* __restrict__ rp, const S
     double2 dot = make_double2(0.0, 0.0);
     for (int r = r0 + grp; r < r1; r += kBlock / G) {
         double2 acc = make_double2(0.0, 0.0);
-        const Src rs = src.row(r);
-        for (int k = rp[r] + lg; k < rp[r + 1]; k += G) {
+        const int kb = rp[r], ke = rp[r + 1];
+        const Src rs = src.row(r, kb);
+        for (int k = kb + lg; k < ke; k += G) {
             int c;
             VT v;
             rs.load(k, c, v);
@@ -1059,8 +1077,9 @@ __global__ __launch_bounds__(kBlock) void k_expand_packed(const int* __restrict_
                                                           int* __restrict__ col, double2* __restrict__ val) {
     for (int r = blockIdx.x * kBlock + threadIdx.x; r < dim; r += gridDim.x * kBlock)
         with_entries(nullptr, nullptr, nullptr, pk, [&](const auto& src) {
-            const auto rs = src.row(r);
-            for (int k = rp[r]; k < rp[r + 1]; ++k) {
+            const int kb = rp[r], ke = rp[r + 1];
+            const auto rs = src.row(r, kb);
+            for (int k = kb; k < ke; ++k) {
                 typename std::decay_t<decltype(src)>::V v;
                 rs.load(k, col[k], v);
                 val[k] = as_complex(v);

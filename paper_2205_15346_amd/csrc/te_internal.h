@@ -86,11 +86,14 @@ struct RedBuf {
 // tval[q], except q = dcode, the row's diagonal: column r, value (diag[r], 0).  Codes are one
 // byte when there are at most 255 distinct (column offset, value) pairs off the diagonal, else
 // two bytes.  Value codes: when the pairs are too many but the values few, col keeps every
-// entry's column and the codes index values only (toff is then all zero).
+// entry's column and the codes index values only (toff is then all zero); codes and columns
+// are then sliced: rows in chunks of 64, entry q of row r at slice[r / 64] + 64 q + r % 64
+// (a chunk is as wide as its longest row).
 struct Packed {
     const uint8_t* c8 = nullptr;    // 1-byte codes, or
     const uint16_t* c16 = nullptr;  // 2-byte codes (at most one is set)
-    const int* col = nullptr;       // value codes: the columns; else unset
+    const int* col = nullptr;       // value codes: the columns (sliced); else unset
+    const int* slice = nullptr;     // value codes: [ceil(dim / 64)] chunk offsets
     const int* toff = nullptr;      // [dcode + 1] column offsets, toff[dcode] = 0
     const double2* tval = nullptr;  // [dcode + 1] values
     const double* diag = nullptr;   // [dim] real diagonal (0 where a row has none)
@@ -247,7 +250,7 @@ inline bool is_packed(const Packed& p) { return p.c8 != nullptr || p.c16 != null
 // real diagonal per row
 inline double csr_entries_bytes(const Csr& c) {
     const double nnz = (double)c.nnz, d = (double)c.dim;
-    const double cols = c.pk.col ? 4.0 * nnz : 0.0;
+    const double cols = c.pk.col ? 4.0 * nnz : 0.0;  // the sliced padding is not counted
     if (c.pk.c8) return 1.0 * nnz + cols + 8.0 * d;
     if (c.pk.c16) return 2.0 * nnz + cols + 8.0 * d;
     return (c.rval ? 12.0 : 20.0) * nnz;
@@ -377,6 +380,7 @@ struct te_hamiltonian_s {
     double2* val = nullptr;
     double* rval = nullptr;
     void* code = nullptr;      // packed entries: codes, table and diagonal
+    int* slice = nullptr;      // value codes: chunk offsets
     int* toff = nullptr;
     double2* tval = nullptr;
     double* diag = nullptr;
