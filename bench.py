@@ -366,7 +366,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="xxz_L20")
     ap.add_argument("--cpu-restarts", type=int, default=2, help="restarts of the CPU oracle sample (0: skip)")
-    ap.add_argument("--shape", default="1,8,4,2,1",
+    ap.add_argument("--shape", default="1,8,4,2,0",
                     help="projection kernel shape lanes,nnz,rows,update_rows,split for the single solve "
                          "(default: the shape te_autotune selects for this matrix on MI355X), or 'auto'")
     ap.add_argument("--three-term", type=int, default=1, help="also time the three-term mode (0: skip)")
