@@ -45,3 +45,20 @@ def random_hermitian_csr(d, density, seed, scale=1.0):
     A = A.tocoo()
     A.sum_duplicates()
     return from_triplets(d, A.row, A.col, A.data, f"rand_d{d}_s{seed}")
+
+
+def few_values_hermitian(d, density, seed, n_values):
+    """A random Hermitian pattern whose entries take n_values values (and their conjugates): too
+    many (column - row, value) pairs to pack, few values."""
+    from workloads.csr import CSR
+    R = random_hermitian_csr(d, density, seed)
+    rng = np.random.default_rng(seed + 1)
+    table = rng.standard_normal(n_values) + 1j * rng.standard_normal(n_values)
+    rows = np.repeat(np.arange(d), np.diff(R.row_ptr)).astype(np.int64)
+    col = R.col.astype(np.int64)
+    lo, hi = np.minimum(rows, col), np.maximum(rows, col)
+    mixed = ((lo.astype(np.uint64) * np.uint64(0x9E3779B1) + hi.astype(np.uint64)) * np.uint64(0x85EBCA6B)) >> np.uint64(13)
+    v = table[(mixed % np.uint64(n_values)).astype(np.int64)]
+    v = np.where(rows < col, v, np.conj(v))
+    v = np.where(rows == col, v.real + 0j, v)
+    return CSR(d, R.row_ptr, R.col, np.ascontiguousarray(v), f"few_values_{n_values}")
