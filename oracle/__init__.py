@@ -18,7 +18,12 @@ Readings of points where the paper is silent or garbled are listed in the
 module docstrings; every function there names the passage it follows.
 Parity status: every function is pinned by a `-m "not gpu"` test (dense exact
 solutions, closed forms, invariants, an arbitrary-precision quadrature, the
-paper's forward-backward example); none is "parity unpinned".
+paper's forward-backward example).  The step search's substep loop (reading R4)
+is pinned on its own: the error it attaches to each accepted step must equal the
+integral over [0, tau] computed without the oracle's quadrature (closed forms,
+an integrand whose only feature lies in the first substep interval, QUADPACK on
+integrands captured from evolutions), and the literal bounds of the printed loop,
+planted, fail those pins.  None is "parity unpinned".
 """
 
 from .quadrature import gauss_legendre, tanh_sinh, QuadratureResult
