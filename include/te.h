@@ -276,6 +276,24 @@ te_status te_set_allocator(te_alloc_fn alloc, te_free_fn free_fn, void* ctx);
 te_status te_evolve(te_hamiltonian h, const te_c128* v0, te_c128* v_out, double t, double tol,
                     int32_t m, const te_options* opt, te_result* res, void* stream);
 
+/* te_evolve_noalloc: for callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid allocation).  The same evolution as
+ * te_evolve, with the same arguments, results, errors and kernels (the handle's current
+ * kernel shape; this call never autotunes), but the workspace (Krylov basis, product vector,
+ * reduction partials, device state, done flag) lives in one static device array of
+ * TE_NOALLOC_SCRATCH_BYTES per device, set up on the first call on each device, instead of
+ * memory the library allocates: the call makes no device or pinned-host allocation.
+ * Limit: te_workspace_bytes(dim, m) + 256 must not exceed TE_NOALLOC_SCRATCH_BYTES (64 MiB:
+ * dim up to ~100,000 at m = 40, e.g. the XXZ ring up to L = 16), else TE_ERR_CAPACITY before
+ * any device work.  TE_OPT_PROFILE is rejected (TE_ERR_INVALID_ARG).  The array keeps the
+ * last call's contents, which the call clears as needed.  Every call on one device shares the
+ * array, so calls that overlapped on one device would race: the library serialises them with a
+ * per-device lock (each process holds its own copy of the array).  The host checks the
+ * device's done flag every two restarts with a 4-byte copy.  Synchronous. */
+#define TE_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+te_status te_evolve_noalloc(te_hamiltonian h, const te_c128* v0, te_c128* v_out, double t, double tol,
+                            int32_t m, const te_options* opt, te_result* res, void* stream);
+
 /* Intermediate-time sampling (second remark after Alg. 1): inside the step that holds t_s,
  * v(t_s) = V exp(-i J (t_s - t_now)) e_1 from the step's own basis and small matrix, so the
  * samples cost no extra Krylov builds.  Each sample carries the bound accumulated up to the

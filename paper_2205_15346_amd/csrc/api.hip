@@ -1168,18 +1168,52 @@ hipError_t enqueue_restart_sampled(te_hamiltonian h, Workspace* w, const SampleB
     return e;
 }
 
-te_status evolve_impl(te_hamiltonian h, const te_c128* v0, te_c128* v_out, double t, double tol, int32_t m,
-                      const te_options* opt, te_result* res, void* stream, SampleBuffers* sb,
-                      DevState* header_out) {
+// The result record of a finished evolution from the device state's header, and the state's
+// own failure status (step underflow, non-finite values, eigensolver failure).
+te_status finish_result(const DevState& hs, double t, te_result* res) {
+    if (res) {
+        res->steps = hs.steps;
+        res->matvecs = hs.matvecs;
+        res->breakdown_dim = hs.breakdown_dim;
+        res->warnings = (uint32_t)hs.warnings;
+        res->err_bound = hs.beta0 * hs.err_acc;
+        res->num_err_estimate = hs.beta0 * hs.num_acc;
+        res->t_reached = hs.t_now;
+    }
+    if (hs.status != TE_OK) {
+        if (hs.status == TE_ERR_STEP_UNDERFLOW)
+            return fail(hs.status, "no admissible step after max_halvings halvings (t_now=" + std::to_string(hs.t_now) + ")");
+        if (hs.status == TE_ERR_NONFINITE) return fail(hs.status, "non-finite value in v0 or during the iteration");
+        return fail(hs.status, "device-side failure (eigensolver did not converge)");
+    }
+    if (hs.beta0 == 0.0 && res) res->t_reached = t;
+    return TE_OK;
+}
+
+te_status reached_end(const DevState& hs, double t) {
+    if (hs.beta0 != 0.0 && hs.t_now != t)
+        return fail(TE_ERR_DEVICE, "evolution stopped at t=" + std::to_string(hs.t_now) + " before reaching t");
+    return TE_OK;
+}
+
+// The argument rules shared by te_evolve and te_evolve_noalloc.
+te_status check_evolve_args(te_hamiltonian h, const te_c128* v0, const te_c128* v_out, double t, double tol,
+                            int32_t m, const te_options* opt, te_options* o) {
     if (!h || !v0 || !v_out) return fail(TE_ERR_INVALID_ARG, "null pointer");
     if (!std::isfinite(t) || t < 0.0) return fail(TE_ERR_INVALID_ARG, "t must be finite and >= 0");
     if (!std::isfinite(tol) || !(tol > 0.0)) return fail(TE_ERR_INVALID_ARG, "tol must be finite and > 0");
     if (m < 2) return fail(TE_ERR_INVALID_ARG, "m must be >= 2");
     if (m > TE_MAX_KRYLOV) return fail(TE_ERR_UNSUPPORTED, "m > TE_MAX_KRYLOV");
+    te_default_options(o);
+    if (opt) *o = *opt;
+    return check_options(*o);
+}
+
+te_status evolve_impl(te_hamiltonian h, const te_c128* v0, te_c128* v_out, double t, double tol, int32_t m,
+                      const te_options* opt, te_result* res, void* stream, SampleBuffers* sb,
+                      DevState* header_out) {
     te_options o;
-    te_default_options(&o);
-    if (opt) o = *opt;
-    te_status rc = check_options(o);
+    te_status rc = check_evolve_args(h, v0, v_out, t, tol, m, opt, &o);
     if (rc != TE_OK) return rc;
     hipStream_t s = (hipStream_t)stream;
     const int dim = h->csr.dim;
@@ -1255,22 +1289,8 @@ te_status evolve_impl(te_hamiltonian h, const te_c128* v0, te_c128* v_out, doubl
     }
     TE_HIP(hipStreamSynchronize(s));
     if (header_out) *header_out = hs;
-    if (res) {
-        res->steps = hs.steps;
-        res->matvecs = hs.matvecs;
-        res->breakdown_dim = hs.breakdown_dim;
-        res->warnings = (uint32_t)hs.warnings;
-        res->err_bound = hs.beta0 * hs.err_acc;
-        res->num_err_estimate = hs.beta0 * hs.num_acc;
-        res->t_reached = hs.t_now;
-    }
-    if (hs.status != TE_OK) {
-        if (hs.status == TE_ERR_STEP_UNDERFLOW)
-            return fail(hs.status, "no admissible step after max_halvings halvings (t_now=" + std::to_string(hs.t_now) + ")");
-        if (hs.status == TE_ERR_NONFINITE) return fail(hs.status, "non-finite value in v0 or during the iteration");
-        return fail(hs.status, "device-side failure (eigensolver did not converge)");
-    }
-    if (hs.beta0 == 0.0 && res) res->t_reached = t;
+    rc = finish_result(hs, t, res);
+    if (rc != TE_OK) return rc;
     if (std::getenv("TE_TRACE")) {
         DevState* full = new (std::nothrow) DevState();
         if (full && hipMemcpy(full, w->st, sizeof(DevState), hipMemcpyDeviceToHost) == hipSuccess) {
@@ -1288,9 +1308,103 @@ te_status evolve_impl(te_hamiltonian h, const te_c128* v0, te_c128* v_out, doubl
         }
         delete full;
     }
-    if (hs.beta0 != 0.0 && hs.t_now != t)
-        return fail(TE_ERR_DEVICE, "evolution stopped at t=" + std::to_string(hs.t_now) + " before reaching t");
+    return reached_end(hs, t);
+}
+
+// ------------------------------------------------------------ evolution without allocation
+// te_evolve_noalloc runs the same kernels as te_evolve with its workspace (basis, product
+// vector, reduction partials, device state, done flag) carved out of one file-scope device
+// array instead of device memory the library allocates.  The array exists once per device
+// (each device's code object holds its own copy, for the life of the process); host code
+// never names it in a launch or copy, only through the address hipGetSymbolAddress returns
+// for the current device on the first call there.
+constexpr size_t kNoallocScratchBytes = (size_t)TE_NOALLOC_SCRATCH_BYTES;
+constexpr int kNoallocMaxDevices = 64;
+constexpr size_t kNoallocFlagBytes = 256;  // the done flag and restart records, first in the array
+
+__device__ __align__(256) char scratch[kNoallocScratchBytes];
+
+std::mutex g_scratch_mu[kNoallocMaxDevices];     // one caller at a time per device
+char* g_scratch_ptr[kNoallocMaxDevices] = {};     // device address of `scratch`, per device
+
+// the scratch address on the current device (looked up once per device; caller holds the
+// device's mutex)
+te_status scratch_address(int dev, char** out) {
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(TE_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = (char*)p;
+    }
+    *out = g_scratch_ptr[dev];
     return TE_OK;
+}
+
+// Workspace view over the scratch array.  base stays null so that nothing is ever freed.
+te_status noalloc_workspace(te_hamiltonian h, int m, char* sp, Workspace* w) {
+    w->dim = h->csr.dim;
+    w->m = m;
+    w->ld = (int64_t)basis_ld(w->dim);
+    w->tl = handle_tiling(h);
+    size_t oy, op, on, orr, os;
+    const size_t bytes = Workspace::layout(w->dim, m, w->tl, &oy, &op, &on, &orr, &os);
+    if (bytes + kNoallocFlagBytes > kNoallocScratchBytes)
+        return fail(TE_ERR_CAPACITY, "te_evolve_noalloc: dim " + std::to_string(w->dim) + " with m " +
+                                         std::to_string(m) + " needs " + std::to_string(bytes + kNoallocFlagBytes) +
+                                         " bytes of scratch, the maximum is " + std::to_string(kNoallocScratchBytes));
+    char* ws = sp + kNoallocFlagBytes;
+    w->bytes = bytes;
+    w->V = (double2*)ws;
+    w->y = (double2*)(ws + oy);
+    w->rb.part = (double2*)(ws + op);
+    w->rb.npart = (double*)(ws + on);
+    w->rb.red = (double2*)(ws + orr);
+    w->rb.n_tiles = w->tl.n_tiles_p;
+    w->rb.n_norm = w->tl.n_tiles_u;
+    w->st = (DevState*)(ws + os);
+    w->host_flag_dev = (int*)sp;  // device memory here, read back with a copy
+    return TE_OK;
+}
+
+te_status evolve_noalloc_locked(te_hamiltonian h, const te_c128* v0, te_c128* v_out, double t, double tol,
+                                int32_t m, const te_options& o, te_result* res, hipStream_t s, char* sp) {
+    const int dim = h->csr.dim;
+    if (t == 0.0) {
+        if (v_out != v0) TE_HIP(hipMemcpyAsync(v_out, v0, (size_t)dim * sizeof(te_c128), hipMemcpyDeviceToDevice, s));
+        TE_HIP(hipStreamSynchronize(s));
+        return TE_OK;
+    }
+    const int mm = std::min(m, dim);
+    Workspace w;
+    te_status rc = noalloc_workspace(h, mm, sp, &w);
+    if (rc != TE_OK) return rc;
+    // the array keeps the previous call's contents: clear the flags, the folded values and the
+    // device state, as a fresh workspace starts
+    TE_HIP(hipMemsetAsync(sp, 0, kNoallocFlagBytes, s));
+    TE_HIP(hipMemsetAsync(w.rb.red, 0, (size_t)kMaxVals * sizeof(double2), s));
+    TE_HIP(hipMemsetAsync(w.st, 0, sizeof(DevState), s));
+    const Problem prob = make_problem(h, o, t, tol, mm);
+    TE_HIP(launch_setup(w.st, prob, s));
+    TE_HIP(launch_copy((const double2*)v0, w.V, dim, s));
+    // Two restarts per check of the done flag: the second is a no-op when the first finished.
+    const long max_restarts = 100000000L;
+    for (long r = 0;; r += 2) {
+        TE_HIP(enqueue_restart(h, &w, s));
+        TE_HIP(enqueue_restart(h, &w, s));
+        int done = 0;
+        TE_HIP(hipMemcpyAsync(&done, w.host_flag_dev, sizeof(int), hipMemcpyDeviceToHost, s));
+        TE_HIP(hipStreamSynchronize(s));
+        if (done) break;
+        if (r >= max_restarts) return fail(TE_ERR_DEVICE, "restart limit reached");
+    }
+    TE_HIP(launch_output(w.V, (double2*)v_out, dim, w.st, s));
+    DevState hs;
+    TE_HIP(hipMemcpyAsync(&hs, w.st, offsetof(DevState, alpha), hipMemcpyDeviceToHost, s));
+    TE_HIP(hipStreamSynchronize(s));
+    rc = finish_result(hs, t, res);
+    if (rc != TE_OK) return rc;
+    return reached_end(hs, t);
 }
 
 }  // namespace
@@ -1300,6 +1414,24 @@ extern "C" {
 te_status te_evolve(te_hamiltonian h, const te_c128* v0, te_c128* v_out, double t, double tol, int32_t m,
                     const te_options* opt, te_result* res, void* stream) {
     return evolve_impl(h, v0, v_out, t, tol, m, opt, res, stream, nullptr, nullptr);
+}
+
+te_status te_evolve_noalloc(te_hamiltonian h, const te_c128* v0, te_c128* v_out, double t, double tol,
+                            int32_t m, const te_options* opt, te_result* res, void* stream) {
+    te_options o;
+    te_status rc = check_evolve_args(h, v0, v_out, t, tol, m, opt, &o);
+    if (rc != TE_OK) return rc;
+    if (o.flags & TE_OPT_PROFILE) return fail(TE_ERR_INVALID_ARG, "te_evolve_noalloc takes no TE_OPT_PROFILE");
+    if (res) std::memset(res, 0, sizeof(*res));
+    int dev = -1;
+    TE_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNoallocMaxDevices) return fail(TE_ERR_UNSUPPORTED, "device ordinal beyond 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu[dev]);
+    char* sp = nullptr;
+    rc = scratch_address(dev, &sp);
+    if (rc != TE_OK) return rc;
+    std::lock_guard<std::mutex> hlock(h->mu);
+    return evolve_noalloc_locked(h, v0, v_out, t, tol, m, o, res, (hipStream_t)stream, sp);
 }
 
 te_status te_evolve_sampled(te_hamiltonian h, const te_c128* v0, te_c128* v_out, double t, double tol,

@@ -34,6 +34,7 @@ TE_STORAGE_COMPLEX, TE_STORAGE_REAL, TE_STORAGE_PACKED8, TE_STORAGE_PACKED16 = 0
 TE_STORAGE_CODED8, TE_STORAGE_CODED16 = 4, 5
 STORAGE_NAMES = {0: "complex", 1: "real", 2: "packed8", 3: "packed16", 4: "coded8", 5: "coded16"}
 TE_MAX_KRYLOV = 64
+TE_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class te_c128(ctypes.Structure):
@@ -164,6 +165,8 @@ _SIGS = {
     "te_workspace_bytes": (ctypes.c_size_t, [_I64, _I]),
     "te_set_allocator": (_I, [_P, _P, _P]),
     "te_evolve": (_I, [_P, _P, _P, _D, _D, _I, ctypes.POINTER(te_options), ctypes.POINTER(te_result), _P]),
+    "te_evolve_noalloc": (_I, [_P, _P, _P, _D, _D, _I, ctypes.POINTER(te_options), ctypes.POINTER(te_result),
+                               _P]),
     "te_last_profile": (_I, [_P, ctypes.POINTER(te_profile)]),
     "te_evolve_sampled": (_I, [_P, _P, _P, _D, _D, _I, ctypes.POINTER(te_options), ctypes.POINTER(te_samples),
                                ctypes.POINTER(te_result), _P]),
@@ -372,6 +375,18 @@ def te_evolve(H: Hamiltonian, v0, t: float, tol: float, m: int, options=None, ou
     res = te_result()
     opt = ctypes.byref(options) if options is not None else None
     _check(_lib.te_evolve(H.handle, p0, p1, float(t), float(tol), int(m), opt, ctypes.byref(res), _stream(stream)))
+    return out, res
+
+
+def te_evolve_noalloc(H: Hamiltonian, v0, t: float, tol: float, m: int, out, options=None, stream=None):
+    """te_evolve with the workspace in the library's static per-device scratch array (no device
+    allocation by the library); ``out`` must be given.  Returns (out, te_result)."""
+    p0 = _dev_c128(v0, "v0", H.dim)
+    p1 = _dev_c128(out, "out", H.dim)
+    res = te_result()
+    opt = ctypes.byref(options) if options is not None else None
+    _check(_lib.te_evolve_noalloc(H.handle, p0, p1, float(t), float(tol), int(m), opt, ctypes.byref(res),
+                                  _stream(stream)))
     return out, res
 
 
