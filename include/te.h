@@ -249,15 +249,24 @@ te_status te_hamiltonian_create_bose_chain(te_hamiltonian* out, int32_t K, int32
 te_status te_hamiltonian_destroy(te_hamiltonian h); /* frees everything the handle owns */
 te_status te_hamiltonian_info(te_hamiltonian h, int64_t* dim, int64_t* nnz, double* norm1);
 
-/* Device bytes of the workspace that te_evolve keeps inside the handle for Krylov
- * dimension m (Krylov basis m*dim complex, one work vector, reduction partials, state). */
-size_t te_workspace_bytes(int64_t dim, int32_t m);
+/* Device bytes of the workspace that te_evolve keeps inside handle h for Krylov dimension m
+ * (Krylov basis min(m, dim)*dim complex, one work vector, reduction partials, device state):
+ * what admission control has to reserve besides the handle's own matrix.  0 for a null
+ * handle or m outside 1..TE_MAX_KRYLOV.  Host only. */
+size_t te_workspace_bytes(te_hamiltonian h, int32_t m);
 
-/* Optional allocator hook for device memory that the library allocates (workspaces,
- * handle copies).  NULL restores hipMalloc/hipFree.  Not thread-safe against running
- * calls; set it once at start-up. */
-typedef void* (*te_alloc_fn)(size_t bytes, void* ctx);
-typedef void (*te_free_fn)(void* ptr, void* ctx);
+/* Optional allocator hook for the device memory the library allocates (handle copies of the
+ * matrix, workspaces, engine pools and plans; not te_evolve_noalloc, which allocates nothing).
+ *   alloc(bytes, stream, ctx): returns device memory of at least bytes (NULL on failure);
+ *       stream is the hipStream_t the memory is first used on (NULL = default stream).
+ *   free_(ptr, stream, ctx): returns a block; called after the device has finished with it
+ *       (the library waits for the device first, as hipFree would), with the stream and ctx
+ *       the block was allocated with.
+ * Both NULL restore hipMalloc/hipFree; one NULL is TE_ERR_INVALID_ARG.  Every block goes back
+ * to the allocator that supplied it, also after the hook has been changed.  The callbacks may
+ * be called from the engine's scheduler thread.  Host only; thread-safe. */
+typedef void* (*te_alloc_fn)(size_t bytes, void* stream, void* ctx);
+typedef void (*te_free_fn)(void* ptr, void* stream, void* ctx);
 te_status te_set_allocator(te_alloc_fn alloc, te_free_fn free_fn, void* ctx);
 
 /* ---------------------------------------------------------------------------------------
@@ -283,7 +292,7 @@ te_status te_evolve(te_hamiltonian h, const te_c128* v0, te_c128* v_out, double 
  * reduction partials, device state, done flag) lives in one static device array of
  * TE_NOALLOC_SCRATCH_BYTES per device, set up on the first call on each device, instead of
  * memory the library allocates: the call makes no device or pinned-host allocation.
- * Limit: te_workspace_bytes(dim, m) + 256 must not exceed TE_NOALLOC_SCRATCH_BYTES (64 MiB:
+ * Limit: te_workspace_bytes(h, m) + 256 must not exceed TE_NOALLOC_SCRATCH_BYTES (64 MiB:
  * dim up to ~100,000 at m = 40, e.g. the XXZ ring up to L = 16), else TE_ERR_CAPACITY before
  * any device work.  TE_OPT_PROFILE is rejected (TE_ERR_INVALID_ARG).  The array keeps the
  * last call's contents, which the call clears as needed.  Every call on one device shares the

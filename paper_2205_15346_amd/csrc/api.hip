@@ -15,6 +15,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "te_internal.h"
@@ -25,9 +26,18 @@ namespace {
 
 thread_local std::string g_last_error;
 
+// te_set_allocator hook.  Every block it supplies is recorded with the free function, context
+// and stream it came with, so a block always goes back to the allocator that supplied it.
 te_alloc_fn g_alloc = nullptr;
 te_free_fn g_free = nullptr;
 void* g_alloc_ctx = nullptr;
+struct AllocRecord {
+    te_free_fn free_fn;
+    void* ctx;
+    void* stream;
+};
+std::mutex g_alloc_mu;
+std::unordered_map<void*, AllocRecord> g_alloc_records;
 
 te_status fail(te_status s, const std::string& msg) {
     g_last_error = msg;
@@ -48,9 +58,23 @@ namespace te {
 
 te_status set_error(te_status s, const std::string& msg) { return fail(s, msg); }
 
-void* dev_alloc(size_t bytes) {
+void* dev_alloc(size_t bytes, hipStream_t stream) {
     if (bytes == 0) bytes = 1;
-    if (g_alloc) return g_alloc(bytes, g_alloc_ctx);
+    te_alloc_fn a;
+    AllocRecord rec;
+    {
+        std::lock_guard<std::mutex> lock(g_alloc_mu);
+        a = g_alloc;
+        rec = AllocRecord{g_free, g_alloc_ctx, (void*)stream};
+    }
+    if (a) {  // the callback runs without the lock held
+        void* p = a(bytes, (void*)stream, rec.ctx);
+        if (p) {
+            std::lock_guard<std::mutex> lock(g_alloc_mu);
+            g_alloc_records[p] = rec;
+        }
+        return p;
+    }
     void* p = nullptr;
     if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
     return p;
@@ -58,8 +82,25 @@ void* dev_alloc(size_t bytes) {
 
 void dev_free(void* p) {
     if (!p) return;
-    if (g_free) g_free(p, g_alloc_ctx);
-    else (void)hipFree(p);
+    AllocRecord rec{};
+    bool hooked = false;
+    {
+        std::lock_guard<std::mutex> lock(g_alloc_mu);
+        auto it = g_alloc_records.find(p);
+        if (it != g_alloc_records.end()) {
+            rec = it->second;
+            g_alloc_records.erase(it);
+            hooked = true;
+        }
+    }
+    if (!hooked) {
+        (void)hipFree(p);
+        return;
+    }
+    // hipFree waits for the device; a caching allocator may hand the block out at once, so
+    // wait here the same way before returning it
+    (void)hipDeviceSynchronize();
+    rec.free_fn(p, rec.stream, rec.ctx);
 }
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -148,7 +189,7 @@ Tiling handle_tiling(te_hamiltonian h) {
                        t.split_projection);
 }
 
-te_status make_workspace(te_hamiltonian h, int m, Workspace** out) {
+te_status make_workspace(te_hamiltonian h, int m, hipStream_t s, Workspace** out) {
     auto* w = new (std::nothrow) Workspace();
     if (!w) return fail(TE_ERR_OUT_OF_MEMORY, "host allocation failed");
     w->dim = h->csr.dim;
@@ -157,7 +198,7 @@ te_status make_workspace(te_hamiltonian h, int m, Workspace** out) {
     w->tl = handle_tiling(h);
     size_t oy, op, on, orr, os;
     w->bytes = Workspace::layout(w->dim, m, w->tl, &oy, &op, &on, &orr, &os);
-    w->base = (char*)dev_alloc(w->bytes);
+    w->base = (char*)dev_alloc(w->bytes, s);
     if (!w->base) {
         delete w;
         return fail(TE_ERR_OUT_OF_MEMORY, "workspace allocation of " + std::to_string(w->bytes) + " bytes failed");
@@ -408,7 +449,7 @@ bool autotune_enabled() {
     return !(v && v[0] == '0');
 }
 
-te_status get_workspace(te_hamiltonian h, int m, Workspace** out) {
+te_status get_workspace(te_hamiltonian h, int m, hipStream_t s, Workspace** out) {
     if (h->ws && h->ws->m == m) {
         *out = h->ws;
         return TE_OK;
@@ -416,7 +457,7 @@ te_status get_workspace(te_hamiltonian h, int m, Workspace** out) {
     delete h->ws;
     h->ws = nullptr;
     Workspace* w = nullptr;
-    te_status rc = make_workspace(h, m, &w);
+    te_status rc = make_workspace(h, m, s, &w);
     if (rc != TE_OK) return rc;
     h->ws = w;
     rc = ensure_graph(h, w);
@@ -495,17 +536,19 @@ const char* te_last_error(void) { return g_last_error.c_str(); }
 
 te_status te_set_allocator(te_alloc_fn alloc, te_free_fn free_fn, void* ctx) {
     if ((alloc == nullptr) != (free_fn == nullptr)) return fail(TE_ERR_INVALID_ARG, "alloc and free must be set together");
+    std::lock_guard<std::mutex> lock(g_alloc_mu);
     g_alloc = alloc;
     g_free = free_fn;
     g_alloc_ctx = ctx;
     return TE_OK;
 }
 
-size_t te_workspace_bytes(int64_t dim, int32_t m) {
-    if (dim < 1 || dim >= (int64_t)1 << 31 || m < 1) return 0;
-    const int mm = (int)std::min<int64_t>(m, dim);
+size_t te_workspace_bytes(te_hamiltonian h, int32_t m) {
+    if (!h || m < 1 || m > TE_MAX_KRYLOV) return 0;
+    const int dim = h->csr.dim;
+    const int mm = std::min(m, dim);
     size_t a, b, c, d, e;
-    return Workspace::layout((int)dim, mm, default_tiling((int)dim), &a, &b, &c, &d, &e);
+    return Workspace::layout(dim, mm, default_tiling(dim), &a, &b, &c, &d, &e);
 }
 
 // Validates a handle's CSR on the device (structure, column range, finite entries, optionally
@@ -776,11 +819,11 @@ te_status te_hamiltonian_create(te_hamiltonian* out, int64_t dim, int64_t nnz, c
     hipStream_t s = (hipStream_t)stream;
     auto* h = new (std::nothrow) te_hamiltonian_s();
     if (!h) return fail(TE_ERR_OUT_OF_MEMORY, "host allocation failed");
-    h->row_ptr = (int*)dev_alloc((dim + 1) * sizeof(int));
-    h->col = (int*)dev_alloc(nnz * sizeof(int));
-    h->val = (double2*)dev_alloc(nnz * sizeof(double2));
-    double* rowsum = (double*)dev_alloc(dim * sizeof(double) + 64);
-    int* err = (int*)dev_alloc(64);
+    h->row_ptr = (int*)dev_alloc((dim + 1) * sizeof(int), s);
+    h->col = (int*)dev_alloc(nnz * sizeof(int), s);
+    h->val = (double2*)dev_alloc(nnz * sizeof(double2), s);
+    double* rowsum = (double*)dev_alloc(dim * sizeof(double) + 64, s);
+    int* err = (int*)dev_alloc(64, s);
     if (!h->row_ptr || !h->col || !h->val || !rowsum || !err) {
         dev_free(rowsum);
         dev_free(err);
@@ -1228,7 +1271,7 @@ te_status evolve_impl(te_hamiltonian h, const te_c128* v0, te_c128* v_out, doubl
     if (sb && (o.flags & TE_OPT_PROFILE)) return fail(TE_ERR_INVALID_ARG, "sampled evolution takes no TE_OPT_PROFILE");
     const int mm = std::min(m, dim);
     Workspace* w = nullptr;
-    rc = get_workspace(h, mm, &w);
+    rc = get_workspace(h, mm, s, &w);
     if (rc != TE_OK) return rc;
     if (!h->tuned && autotune_enabled()) {
         rc = run_autotune(h, w, s);
@@ -1523,7 +1566,7 @@ te_status te_autotune(te_hamiltonian h, int32_t m, te_tuning* out, void* stream)
     if (m < 1 || m > TE_MAX_KRYLOV) return fail(TE_ERR_INVALID_ARG, "m out of range");
     std::lock_guard<std::mutex> lock(h->mu);
     Workspace* w = nullptr;
-    te_status rc = get_workspace(h, std::min<int>(m, h->csr.dim), &w);
+    te_status rc = get_workspace(h, std::min<int>(m, h->csr.dim), (hipStream_t)stream, &w);
     if (rc != TE_OK) return rc;
     h->tuned = false;
     rc = run_autotune(h, w, (hipStream_t)stream);
@@ -1570,7 +1613,7 @@ te_status te_spmv(te_hamiltonian h, const te_c128* x, te_c128* y, te_c128* xhy, 
     hipStream_t s = (hipStream_t)stream;
     std::lock_guard<std::mutex> lock(h->mu);
     Workspace* w = nullptr;
-    te_status rc = get_workspace(h, h->ws ? h->ws->m : std::min(2, h->csr.dim), &w);
+    te_status rc = get_workspace(h, h->ws ? h->ws->m : std::min(2, h->csr.dim), s, &w);
     if (rc != TE_OK) return rc;
     TE_HIP(launch_spmv_only(w->tl, h->csr, (const double2*)x, (double2*)y, w->st, w->rb, s));
     double2 dot;
@@ -1597,7 +1640,7 @@ te_status te_arnoldi(te_hamiltonian h, const te_c128* u, int32_t m, double tol_r
     const int dim = h->csr.dim;
     const int mm = std::min<int>(m, dim);
     Workspace* w = nullptr;
-    te_status rc = get_workspace(h, mm, &w);
+    te_status rc = get_workspace(h, mm, s, &w);
     if (rc != TE_OK) return rc;
     te_options o;
     te_default_options(&o);

@@ -809,13 +809,13 @@ te_status te_engine_create(te_engine* out, const te_engine_config* cfg, void* st
     };
     chk(hipGetDevice(&e->device), "hipGetDevice");
     if (rc == TE_OK) {
-        e->pool_base = (char*)dev_alloc(cfg->hbm_budget);
+        e->pool_base = (char*)dev_alloc(cfg->hbm_budget, (hipStream_t)stream);
         if (!e->pool_base) rc = set_error(TE_ERR_OUT_OF_MEMORY, "pool allocation of " + std::to_string(cfg->hbm_budget) + " bytes failed");
     }
     if (rc == TE_OK) {
         e->pool.reset(cfg->hbm_budget);
-        e->states = (DevState*)dev_alloc(sizeof(DevState) * (size_t)cfg->max_jobs);
-        e->rounds_dev = (int*)dev_alloc(256);
+        e->states = (DevState*)dev_alloc(sizeof(DevState) * (size_t)cfg->max_jobs, (hipStream_t)stream);
+        e->rounds_dev = (int*)dev_alloc(256, (hipStream_t)stream);
         if (!e->states || !e->rounds_dev) rc = set_error(TE_ERR_OUT_OF_MEMORY, "slot allocation failed");
     }
     if (rc == TE_OK) {

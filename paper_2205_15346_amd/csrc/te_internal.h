@@ -363,8 +363,9 @@ hipError_t launch_obs_fold(const double* obs_part, int n_tiles, int n_values, do
 
 // ------------------------------------------------------------- host-side shared helpers
 te_status set_error(te_status s, const std::string& msg);  // thread-local te_last_error text
-void* dev_alloc(size_t bytes);                             // te_set_allocator hook or hipMalloc
-void dev_free(void* p);
+// te_set_allocator hook or hipMalloc; the stream is the one the memory is first used on
+void* dev_alloc(size_t bytes, hipStream_t stream = nullptr);
+void dev_free(void* p);  // returns a block to the allocator that supplied it
 te_status check_options(const te_options& o);
 size_t align_up(size_t x, size_t a);
 // leading dimension (elements) of a basis: one column per Krylov vector

@@ -162,7 +162,7 @@ _SIGS = {
     "te_hamiltonian_create_memory_burden": (_I, [ctypes.POINTER(_P), ctypes.c_void_p, ctypes.POINTER(_I64), _P]),
     "te_hamiltonian_create_bose_chain": (_I, [ctypes.POINTER(_P), ctypes.c_int32, ctypes.c_int32, _P, _P,
                                               ctypes.c_uint32, _P]),
-    "te_workspace_bytes": (ctypes.c_size_t, [_I64, _I]),
+    "te_workspace_bytes": (ctypes.c_size_t, [_P, _I]),
     "te_set_allocator": (_I, [_P, _P, _P]),
     "te_evolve": (_I, [_P, _P, _P, _D, _D, _I, ctypes.POINTER(te_options), ctypes.POINTER(te_result), _P]),
     "te_evolve_noalloc": (_I, [_P, _P, _P, _D, _D, _I, ctypes.POINTER(te_options), ctypes.POINTER(te_result),
@@ -240,8 +240,55 @@ def te_status_string(status: int) -> str:
     return _lib.te_status_string(status).decode()
 
 
-def te_workspace_bytes(dim: int, m: int) -> int:
-    return int(_lib.te_workspace_bytes(dim, m))
+def te_workspace_bytes(H, m: int) -> int:
+    """Device bytes te_evolve keeps in handle H for Krylov dimension m (0 for H = None)."""
+    return int(_lib.te_workspace_bytes(H.handle if H is not None else None, int(m)))
+
+
+TE_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+TE_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+_allocator_callbacks = []  # installed callbacks stay alive: blocks they supplied may be freed later
+
+
+def te_set_allocator(alloc=None, free=None):
+    """Installs alloc(nbytes, stream) -> device address (int, 0 on failure) and
+    free(address, stream) as the library's device allocator; both None restore hipMalloc/hipFree.
+    ``stream`` is the raw hipStream_t value (0 = default stream)."""
+    if alloc is None and free is None:
+        _check(_lib.te_set_allocator(None, None, None))
+        return
+    if alloc is None or free is None:
+        raise ValueError("alloc and free must be given together")
+
+    def _alloc(nbytes, stream, ctx):
+        try:
+            return int(alloc(int(nbytes), int(stream or 0))) or None
+        except Exception:
+            return None  # the library reports TE_ERR_OUT_OF_MEMORY
+
+    def _free(ptr, stream, ctx):
+        try:
+            free(int(ptr), int(stream or 0))
+        except Exception:
+            pass
+
+    ca, cf = TE_ALLOC_FN(_alloc), TE_FREE_FN(_free)
+    _allocator_callbacks.append((ca, cf))
+    _check(_lib.te_set_allocator(ctypes.cast(ca, ctypes.c_void_p), ctypes.cast(cf, ctypes.c_void_p), None))
+
+
+def torch_caching_allocator(device=None):
+    """(alloc, free) for te_set_allocator over PyTorch's caching allocator on one device."""
+    import torch
+    dev = torch.cuda.current_device() if device is None else int(device)
+
+    def alloc(nbytes, stream):
+        return torch.cuda.caching_allocator_alloc(nbytes, dev, stream)
+
+    def free(ptr, stream):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    return alloc, free
 
 
 class Hamiltonian:

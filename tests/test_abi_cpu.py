@@ -40,11 +40,8 @@ def test_host_only_calls():
             o.max_halvings, o.flags, o.quad_gauss_points) == (10, 0.1, 0.97, 1e-3, 15, 3, 64, 0, 0)
     assert te.te_status_string(te.TE_OK) == "ok"
     assert "step" in te.te_status_string(te.TE_ERR_STEP_UNDERFLOW)
-    # workspace: 40 basis columns + work vector of 2^20 complex numbers, plus small scratch
-    b = te.te_workspace_bytes(1 << 20, 40)
-    assert 41 * (1 << 20) * 16 <= b <= 41 * (1 << 20) * 16 + (16 << 20)
-    assert te.te_workspace_bytes(0, 40) == 0
-    assert te.te_workspace_bytes(100, 200) == te.te_workspace_bytes(100, 100)
+    # the workspace size needs a handle (sizes with one are checked by the GPU tests)
+    assert te.te_workspace_bytes(None, 40) == 0
 
 
 def test_argument_validation_without_device():

@@ -60,9 +60,8 @@ def test_noalloc_capacity_and_arguments():
     te = lib()
     torch_dev()
     H, v0 = workloads.xxz_chain(17, seed=14)  # 131,072 rows x 41 columns: 86 MB > 64 MiB
-    assert te.te_workspace_bytes(H.dim, 40) + 256 > te.TE_NOALLOC_SCRATCH_BYTES
-    assert te.te_workspace_bytes(1 << 16, 40) + 256 <= te.TE_NOALLOC_SCRATCH_BYTES
     with hamiltonian(H) as h:
+        assert te.te_workspace_bytes(h, 40) + 256 > te.TE_NOALLOC_SCRATCH_BYTES
         te.te_set_tuning(h, *SHAPE)
         x = to_dev(v0)
         out = torch.empty_like(x)
@@ -73,7 +72,7 @@ def test_noalloc_capacity_and_arguments():
             te.te_evolve_noalloc(h, x, 1.0, 1e-8, 40, out, options=te.te_default_options(flags=te.TE_OPT_PROFILE))
         assert e.value.status == te.TE_ERR_INVALID_ARG
         # a smaller m fits: 131,072 rows x 25 columns
-        assert te.te_workspace_bytes(H.dim, 24) + 256 <= te.TE_NOALLOC_SCRATCH_BYTES
+        assert te.te_workspace_bytes(h, 24) + 256 <= te.TE_NOALLOC_SCRATCH_BYTES
         got, r = te.te_evolve_noalloc(h, x, 0.5, 1e-8, 24, out)
         ref, rr = te.te_evolve(h, x, 0.5, 1e-8, 24)
         assert np.array_equal(to_host(got), to_host(ref))
