@@ -243,7 +243,7 @@ def krylov_coefficients(lam: np.ndarray, U: np.ndarray, tau: float) -> np.ndarra
 
 def evolve(H, v0: np.ndarray, t: float, tol: float, m: int, opts: Optional[Options] = None,
            norm1: Optional[float] = None, max_steps: Optional[int] = None,
-           three_term: bool = False, sample_times=None) -> EvolveResult:
+           three_term: bool = False, sample_times=None, on_step=None) -> EvolveResult:
     """Alg. 1: approximate exp(-iHt) v0 with the a-posteriori bound of eq. errorIntegral.
 
     ``max_steps`` (harness use only, e.g. timing a bounded sample) stops after that many
@@ -313,6 +313,8 @@ def evolve(H, v0: np.ndarray, t: float, tol: float, m: int, opts: Optional[Optio
         if ar.breakdown:
             breakdown_dim = ar.k
             t_now = t
+        if on_step is not None:
+            on_step(steps, t_now, beta0 * err_acc)
         if max_steps is not None and steps >= max_steps:
             break
     return EvolveResult(beta0 * w, steps, matvecs, beta0 * err_acc, beta0 * num_acc, warnings,

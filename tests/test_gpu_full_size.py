@@ -1,0 +1,105 @@
+"""Parity at the full single-solve sizes, element by element against the oracle's stored states.
+
+tests/golden/make_oracle_states.py ran the CPU oracle (Alg. 1, plain NumPy/SciPy FP64) on the
+full workloads and stored v(t); these tests run the HIP path through the C ABI on the same
+seeded inputs (checked by their SHA-256 digests first) in the kernel shape the benchmark times,
+for each storage of the matrix, and require (Sec. "Analysis of Performance": two
+implementations agree within their bounds)
+  ||v_gpu - v_oracle||_2 <= 2 tol + 1e-12,  bound <= tol,  restarts within one of the oracle's,
+plus, at L = 20 with m = 40, the orthogonality of the device's Krylov basis and its Lanczos
+relation."""
+
+import importlib.util
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.gpu_util import announce, lib, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+EPS = np.finfo(float).eps
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _maker():
+    spec = importlib.util.spec_from_file_location("make_oracle_states", os.path.join(GOLDEN, "make_oracle_states.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def oracle_state(name):
+    mk = _maker()
+    npy, meta_path = mk.state_paths(name)
+    with open(meta_path) as f:
+        meta = json.load(f)
+    v = np.load(npy, allow_pickle=False)
+    return v, meta, mk
+
+
+@pytest.fixture(scope="module")
+def xxz_L20():
+    announce("building xxz_L20 inputs and loading the oracle's state")
+    wl = W.workload("xxz_L20")
+    v_or, meta, mk = oracle_state("xxz_L20")
+    assert mk.input_digest(wl.H, wl.v0) == meta["input_sha256"], "inputs differ from those the oracle ran on"
+    assert (meta["t"], meta["tol"], meta["m"]) == (wl.t, wl.tol, wl.m)
+    return wl, v_or, meta
+
+
+# (storage, kernel shape): the benchmark's headline (packed entries, the shape it pins) and its
+# CSR entry (complex128 CSR kept as given, the shape the autotuner picks for it), plus the
+# headline shape on the CSR
+CASES = [("packed", (1, 8, 4, 2, 0)), ("csr", (8, 2, 4, 2, 1)), ("csr", (1, 8, 4, 2, 0))]
+
+
+@pytest.mark.parametrize("storage,shape", CASES)
+def test_xxz_L20_matches_oracle_state(xxz_L20, storage, shape):
+    te = lib()
+    wl, v_or, meta = xxz_L20
+    announce(f"xxz_L20 vs oracle state: storage={storage} shape={shape}")
+    h = te.te_hamiltonian_create(wl.H.row_ptr, wl.H.col, wl.H.val, store_csr=(storage == "csr"))
+    try:
+        assert h.storage == ("packed8" if storage == "packed" else "complex")
+        te.te_set_tuning(h, *shape)
+        v, res = te.te_evolve(h, to_dev(wl.v0), wl.t, wl.tol, wl.m)
+        v = to_host(v)
+    finally:
+        h.destroy()
+    gap = float(np.linalg.norm(v - v_or))
+    announce(f"  |gpu - oracle| = {gap:.3e}, restarts {res.steps} vs {meta['steps']}, "
+             f"bound {res.err_bound:.6e} vs {meta['err_bound']:.6e}")
+    assert res.t_reached == wl.t
+    assert gap <= 2 * wl.tol + 1e-12
+    assert res.err_bound <= wl.tol
+    assert abs(res.steps - meta["steps"]) <= 1
+    assert res.matvecs == wl.m * res.steps
+    assert res.err_bound == pytest.approx(meta["err_bound"], rel=1e-3) or res.steps != meta["steps"]
+    assert res.warnings == meta["warnings"]  # the roundoff estimate exceeds the bound on both
+
+
+def test_xxz_L20_krylov_basis_orthogonal(xxz_L20):
+    """te_arnoldi at the full size with m = 40 in the benchmark's kernel shape: V^H V = I to
+    1e-12 and H V^T = V^T J + beta_k v_{k+1} e_k^T to rounding."""
+    te = lib()
+    wl, _, _ = xxz_L20
+    announce("xxz_L20 Krylov basis m=40: orthogonality and Lanczos relation")
+    h = te.te_hamiltonian_create(wl.H.row_ptr, wl.H.col, wl.H.val)
+    try:
+        te.te_set_tuning(h, 1, 8, 4, 2, 0)
+        V, alpha, beta, k = te.te_arnoldi(h, to_dev(wl.v0), 40, 1e-12)
+        V = to_host(V)
+    finally:
+        h.destroy()
+    assert k == 40
+    G = V.conj() @ V.T
+    assert np.abs(G - np.eye(k)).max() <= 1e-12
+    A = wl.H.to_scipy()
+    J = np.diag(alpha) + np.diag(beta[:-1], 1) + np.diag(beta[:-1], -1)
+    R = A @ V.T - V.T @ J
+    scale = wl.H.norm1()
+    assert np.linalg.norm(R[:, :-1]) <= 10 * k * EPS * scale
+    assert abs(np.linalg.norm(R[:, -1]) - beta[-1]) <= 10 * k * EPS * scale

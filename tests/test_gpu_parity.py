@@ -354,7 +354,7 @@ def test_error_paths():
 # ------------------------------------------------------------------- autotuned kernel shapes
 SHAPES = [(4, 1, 1, 1, 0), (4, 4, 1, 1, 0), (8, 2, 1, 1, 0), (4, 1, 2, 2, 0), (4, 4, 2, 2, 0), (8, 2, 2, 2, 0),
           (8, 2, 1, 2, 0), (4, 4, 1, 1, 1), (8, 2, 2, 2, 1), (4, 1, 2, 1, 1), (4, 4, 4, 1, 0), (8, 2, 4, 2, 1),
-          (4, 1, 4, 2, 1)]
+          (4, 1, 4, 2, 1), (1, 8, 4, 2, 0), (1, 8, 4, 2, 1), (1, 16, 4, 2, 0), (2, 8, 2, 2, 0)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
@@ -377,7 +377,7 @@ def test_every_kernel_shape_matches_oracle(shape):
         assert abs(res.steps - ro.steps) <= 1
 
 
-@pytest.mark.parametrize("shape", [(4, 4, 1, 1), (8, 2, 2, 2), (4, 1, 2, 1), (8, 2, 4, 2)])
+@pytest.mark.parametrize("shape", [(4, 4, 1, 1), (8, 2, 2, 2), (4, 1, 2, 1), (8, 2, 4, 2), (1, 8, 4, 2)])
 def test_split_projection_is_bitwise_the_fused_one(shape):
     """Sparse product and projections as two launches (y read back from memory) accumulate in
     the same order as the fused kernel: identical results."""

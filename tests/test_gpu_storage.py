@@ -125,7 +125,7 @@ def test_diagonals_that_do_not_pack():
 
 @pytest.mark.parametrize("shape", [(4, 4, 1, 1, 0), (8, 2, 4, 2, 1), (4, 1, 2, 1, 1), (8, 2, 2, 2, 0),
                                    (4, 4, 4, 2, 1), (2, 8, 2, 2, 1), (1, 8, 4, 2, 1), (1, 16, 4, 2, 0),
-                                   (1, 8, 1, 1, 0)])
+                                   (1, 8, 1, 1, 0), (1, 8, 4, 2, 0)])
 @pytest.mark.parametrize("real", [False, True])
 def test_evolve_is_bitwise_across_storage(shape, real):
     announce(f"evolution across storage, shape {shape}, real {real}")
@@ -146,7 +146,8 @@ def test_evolve_is_bitwise_across_storage(shape, real):
 
 
 @pytest.mark.parametrize("n_values", [40, 2000])
-@pytest.mark.parametrize("shape", [(4, 4, 2, 2, 1), (1, 8, 4, 2, 1), (8, 2, 1, 1, 0), (1, 16, 2, 2, 0)])
+@pytest.mark.parametrize("shape", [(4, 4, 2, 2, 1), (1, 8, 4, 2, 1), (8, 2, 1, 1, 0), (1, 16, 2, 2, 0),
+                                   (1, 8, 4, 2, 0)])
 def test_value_codes_evolve_bitwise_and_match_oracle(shape, n_values):
     announce(f"value codes ({n_values} values), shape {shape}")
     te = lib()
@@ -196,7 +197,7 @@ def test_packing_a_device_built_matrix():
         h.destroy()
 
 
-@pytest.mark.parametrize("shape", [(4, 4, 2, 2, 1), (1, 8, 4, 2, 1), (2, 8, 2, 2, 0)])
+@pytest.mark.parametrize("shape", [(4, 4, 2, 2, 1), (1, 8, 4, 2, 1), (2, 8, 2, 2, 0), (1, 8, 4, 2, 0)])
 def test_two_byte_codes_evolve_bitwise_and_match_oracle(shape):
     announce(f"2-byte codes: Bose chain, shape {shape}")
     te = lib()
