@@ -36,11 +36,11 @@ def percentile(xs, q):
     return float(np.percentile(np.asarray(xs), q))
 
 
-def measured_traffic(kernel_source):
-    """HBM bytes per projection launch from the committed counter runs, or None when the kernel
-    source changed since they were taken (profiles/xxz_L20_hbm_traffic.json)."""
+def measured_traffic(kernel_source, record="xxz_L20_hbm_traffic.json"):
+    """HBM bytes per projection launch from a committed counter record under profiles/, or None
+    when the kernel source changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "xxz_L20_hbm_traffic.json")
+    path = os.path.join(ROOT, "profiles", record)
     try:
         rec = json.load(open(path))
         src = hashlib.sha256(open(kernel_source, "rb").read()).hexdigest()
@@ -51,21 +51,31 @@ def measured_traffic(kernel_source):
     return rec
 
 
-def cpu_baseline(wl, gpu_restarts, n_restarts):
-    """The CPU oracle, as it stands, on a bounded sample: its first n_restarts restarts of the same
-    workload, extrapolated to a whole solve with the restart count of the GPU solve."""
-    import oracle
+def cpu_model():
     try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:  # pragma: no cover
-        threads = 1
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(wl, gpu_restarts, n_restarts, single_thread_restarts=1):
+    """The CPU oracle, as it stands, on a bounded sample: its first n_restarts restarts of the same
+    workload on the host's BLAS threads, and single_thread_restarts more with BLAS limited to one
+    thread, each extrapolated to a whole solve with the restart count of the GPU solve."""
+    import oracle
+    from threadpoolctl import threadpool_info, threadpool_limits
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     t0 = time.perf_counter()
     res = oracle.evolve(wl.H, wl.v0, wl.t, wl.tol, wl.m, max_steps=n_restarts)
     dt = time.perf_counter() - t0
     per_restart = dt / max(res.steps, 1)
     solve_s = per_restart * gpu_restarts
-    return {
+    rec = {
         "value": 1.0 / solve_s,
         "unit": "states/s",
         "cores": int(threads),
@@ -73,13 +83,101 @@ def cpu_baseline(wl, gpu_restarts, n_restarts):
         "sample": (f"first {res.steps} restarts of {wl.name} ({dt:.1f} s, {per_restart:.2f} s/restart), "
                    f"extrapolated to the {gpu_restarts} restarts of one solve; sparse product single-threaded "
                    f"(SciPy), BLAS-1 on {threads} OpenBLAS threads"),
+        "cpu_model": cpu_model(),
         "seconds_per_solve": solve_s,
     }
+    if single_thread_restarts > 0:
+        with threadpool_limits(limits=1):
+            t1 = time.perf_counter()
+            r1 = oracle.evolve(wl.H, wl.v0, wl.t, wl.tol, wl.m, max_steps=single_thread_restarts)
+            d1 = time.perf_counter() - t1
+        p1 = d1 / max(r1.steps, 1)
+        rec["single_thread"] = {"value": 1.0 / (p1 * gpu_restarts), "unit": "states/s", "cores": 1,
+                                "sample": f"first {r1.steps} restart(s), {p1:.2f} s/restart, BLAS on one thread"}
+    return rec
 
 
 def kernel_rates(prof):
     return {k: (v["bytes"] / v["seconds"] / 1e9 if v["seconds"] > 0 and v["bytes"] > 0 else None)
             for k, v in prof.items()}
+
+
+def time_solves(te, torch, H, v0, out, wl, steps, warmup, label):
+    """warmup untimed solves, then `steps` solves in profiling mode (HIP events bound to every
+    kernel dispatch, on the call's stream); per-kernel totals, wall time, latencies, last result."""
+    plain = te.te_default_options()
+    prof = te.te_default_options(flags=te.TE_OPT_PROFILE)
+    for i in range(warmup):
+        _, res = te.te_evolve(H, v0, wl.t, wl.tol, wl.m, options=plain, out=out)
+        log(f"[bench] {label} warmup {i}: restarts={res.steps} bound={res.err_bound:.3e}")
+    totals = {k: {"launches": 0, "seconds": 0.0, "bytes": 0.0} for k in te.KERNEL_CLASSES}
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        s = time.perf_counter()
+        _, res = te.te_evolve(H, v0, wl.t, wl.tol, wl.m, options=prof, out=out)
+        lat.append(time.perf_counter() - s)
+        p = te.te_last_profile(H).as_dict()
+        for k in totals:
+            for f in totals[k]:
+                totals[k][f] += p[k][f]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    log(f"[bench] {label}: {steps} solves in {elapsed:.3f} s; restarts/solve={res.steps} bound={res.err_bound:.3e}")
+    return {"totals": totals, "elapsed": elapsed, "lat": lat, "res": res}
+
+
+def roofline_of(totals, traffic=None):
+    """Roofline entry of the dominant kernel class: its algorithmic bytes over the summed
+    durations of its launches (HIP events on the call's stream)."""
+    dominant = max(totals, key=lambda k: totals[k]["seconds"])
+    dom = totals[dominant]
+    achieved = dom["bytes"] / dom["seconds"] / 1e9
+    return {"bound": "hbm", "kernel": dominant, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "algorithmic_bytes_per_launch": dom["bytes"] / max(dom["launches"], 1)}
+
+
+def survey_bytes_per_restart(d, nnz, m):
+    """Algorithmic bytes of one restart's Krylov build with full Gram-Schmidt and the matrix as
+    complex CSR (20 bytes per entry): iteration j = 1..m moves 20 nnz + 4 (d + 1) + 16 d (2j + 5)."""
+    return sum(20.0 * nnz + 4.0 * (d + 1) + 16.0 * d * (2 * j + 5) for j in range(1, m + 1))
+
+
+def spmv_orth_rates(totals, d, nnz, m, restarts_total):
+    """Sparse product + orthogonalisation (projection, fold and update kernels together): the
+    library's own algorithmic bytes and the complex-CSR bytes of the formula above, each over the
+    same kernel time."""
+    ks = ("project", "fold", "update")
+    sec = sum(totals[k]["seconds"] for k in ks)
+    own = sum(totals[k]["bytes"] for k in ks) / sec / 1e9
+    csr = survey_bytes_per_restart(d, nnz, m) * restarts_total / sec / 1e9
+    return {"kernels": list(ks), "gbs": own, "frac_of_peak": own / HBM_PEAK_GBS,
+            "gbs_on_complex_csr_bytes": csr, "frac_on_complex_csr_bytes": csr / HBM_PEAK_GBS}
+
+
+def bench_workload(te, torch, dev, name, steps, warmup, shape="auto", store_csr=False):
+    """One single-solve configuration other than the headline, timed like the headline."""
+    import workloads
+    wl = workloads.workload(name)
+    H = te.te_hamiltonian_create(wl.H.row_ptr, wl.H.col, wl.H.val, store_csr=store_csr)
+    v0 = torch.from_numpy(wl.v0).to(dev)
+    out = torch.empty_like(v0)
+    if shape != "auto":
+        te.te_set_tuning(H, *shape)
+    r = time_solves(te, torch, H, v0, out, wl, steps, warmup, name)
+    res = r["res"]
+    rec = {"workload": name, "dim": wl.H.dim, "nnz": wl.H.nnz, "t": wl.t, "tol": wl.tol, "m": wl.m,
+           "storage": H.storage, "kernel_shape": te.te_get_tuning(H).as_dict(),
+           "value": steps / r["elapsed"], "unit": "states/s", "ms_per_step": 1e3 * r["elapsed"] / steps,
+           "restarts_per_solve": res.steps, "matvecs_per_solve": res.matvecs, "err_bound": res.err_bound,
+           "warnings": res.warnings, "roofline": roofline_of(r["totals"]),
+           "spmv_orthogonalisation": spmv_orth_rates(r["totals"], wl.H.dim, wl.H.nnz, wl.m, res.steps * steps),
+           "kernel_ms_per_solve": {k: 1e3 * v["seconds"] / steps for k, v in r["totals"].items()}}
+    H.destroy()
+    return rec
 
 
 def bench_three_term(te, torch, H, v0, out, wl, steps):
@@ -311,10 +409,12 @@ def bench_paper_model(te, torch, dev, packed_only=False):
     i9-9900K, 353 s; roundoff estimate 3.2e-6) is context, not a comparison on equal hardware."""
     import workloads
     params = dict(K=10, Kp=10, Nm=5, N0=100, Nc=100.0)
-    b0 = time.perf_counter()
-    H, _, _ = workloads.memory_burden_model(**params)  # host builder: basis, lookup, triplets
-    host_build_s = time.perf_counter() - b0
-    del H
+    host_build_s = None
+    if not packed_only:
+        b0 = time.perf_counter()
+        H, _, _ = workloads.memory_burden_model(**params)  # host builder: basis, lookup, triplets
+        host_build_s = time.perf_counter() - b0
+        del H
     torch.cuda.synchronize()
     b0 = time.perf_counter()
     h, idx = te.te_hamiltonian_create_memory_burden(**params)  # the same matrix built on the device
@@ -323,7 +423,7 @@ def bench_paper_model(te, torch, dev, packed_only=False):
     x = torch.zeros(h.dim, dtype=torch.complex128, device=dev)
     x[idx] = 1.0  # eq. initialStateSimple
     dim, nnz = h.dim, h.nnz
-    log(f"[bench] paper model built on the device in {build_s:.3f} s (host builder {host_build_s:.1f} s)")
+    log(f"[bench] paper model built on the device in {build_s:.3f} s (host builder: {host_build_s} s)")
     def timed():
         te.te_evolve(h, x, 10.0, 1e-7, 40)  # warm-up and autotune
         times = []
@@ -380,9 +480,13 @@ def main():
     ap.add_argument("--serve-saturation", type=int, default=0, help="first measure saturation (all arrive at 0)")
     ap.add_argument("--serve-sweep", default="", help="comma-separated QPS values for a sweep")
     ap.add_argument("--serve-sweep-requests", type=int, default=48)
-    ap.add_argument("--paper-model", type=int, default=0,
-                    help="also time the paper's own performance example (d = 1,565,904): 1 = as built "
-                         "(real CSR) and packed, 2 = packed only")
+    ap.add_argument("--paper-model", type=int, default=2,
+                    help="also time the paper's own performance example (d = 1,565,904), built on the device: "
+                         "1 = as built (real CSR) and packed, plus the host builder's time; 2 = packed only; "
+                         "0 = skip")
+    ap.add_argument("--bose-solves", type=int, default=2,
+                    help="timed solves of the Bose chain K = N = 12 (d = 1,352,078, t = 50, tol = 1e-10, "
+                         "m = 60; 0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         log("bench.py measures one GPU: this build has no multi-GPU path (independent solves shard "
@@ -403,34 +507,18 @@ def main():
     v0 = torch.from_numpy(wl.v0).to(dev)
     out = torch.empty_like(v0)
     plain = te.te_default_options()
-    prof = te.te_default_options(flags=te.TE_OPT_PROFILE)
 
     if args.shape != "auto":
         te.te_set_tuning(H, *[int(x) for x in args.shape.split(",")])
-    for i in range(args.warmup):
-        _, res = te.te_evolve(H, v0, wl.t, wl.tol, wl.m, options=plain, out=out)
-        log(f"[bench] warmup {i}: restarts={res.steps} bound={res.err_bound:.3e}")
-
+    if args.warmup > 0:
+        _, res = te.te_evolve(H, v0, wl.t, wl.tol, wl.m, options=plain, out=out)  # autotunes when asked
     tuning = te.te_get_tuning(H).as_dict()
     log(f"[bench] kernel shape: {tuning}")
 
     # ---- timed region (profiling mode: events around every kernel, on the call's stream)
-    totals = {k: {"launches": 0, "seconds": 0.0, "bytes": 0.0} for k in te.KERNEL_CLASSES}
-    lat = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        s = time.perf_counter()
-        _, res = te.te_evolve(H, v0, wl.t, wl.tol, wl.m, options=prof, out=out)
-        lat.append(time.perf_counter() - s)
-        p = te.te_last_profile(H).as_dict()
-        for k in totals:
-            for f in totals[k]:
-                totals[k][f] += p[k][f]
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    head = time_solves(te, torch, H, v0, out, wl, args.steps, max(args.warmup - 1, 0), wl.name)
+    totals, elapsed, lat, res = head["totals"], head["elapsed"], head["lat"], head["res"]
     restarts, matvecs, bound = res.steps, res.matvecs, res.err_bound
-    log(f"[bench] timed {args.steps} solves in {elapsed:.3f} s; restarts/solve={restarts}")
 
     # ---- same solves in graph mode (informational)
     torch.cuda.synchronize()
@@ -443,23 +531,18 @@ def main():
     # ---- three-term mode (TE_OPT_LANCZOS3; informational, not the headline)
     three_term = bench_three_term(te, torch, H, v0, out, wl, args.steps) if args.three_term else None
 
-    # ---- the same solves with the matrix kept as CSR (TE_STORE_CSR; informational)
+    # ---- the same workload with the matrix kept as complex CSR (TE_STORE_CSR), in the shape the
+    # autotuner picks for it, timed the same way (informational)
     csr = None
     if args.csr_storage:
-        Hc = te.te_hamiltonian_create(wl.H.row_ptr, wl.H.col, wl.H.val, store_csr=True)
-        te.te_set_tuning(Hc, 8, 2, 4, 2, 1)  # the fastest whole-solve shape on the CSR (measured)
-        te.te_evolve(Hc, v0, wl.t, wl.tol, wl.m, options=plain, out=out)  # warm-up
-        torch.cuda.synchronize()
-        c0 = time.perf_counter()
-        for i in range(args.steps):
-            _, rc = te.te_evolve(Hc, v0, wl.t, wl.tol, wl.m, options=plain, out=out)
-        torch.cuda.synchronize()
-        csr_elapsed = time.perf_counter() - c0
-        csr = {"storage": Hc.storage, "ms_per_step": 1e3 * csr_elapsed / args.steps,
-               "value": args.steps / csr_elapsed, "restarts_per_solve": rc.steps,
-               "kernel_shape": te.te_get_tuning(Hc).as_dict()}
-        Hc.destroy()
-        log(f"[bench] CSR storage ({csr['storage']}): {csr['ms_per_step']:.1f} ms per solve")
+        csr = bench_workload(te, torch, dev, wl.name, min(args.steps, 5), 1, shape=(8, 2, 4, 2, 1),
+                             store_csr=True)
+        csr_traffic = measured_traffic(os.path.join(ROOT, "paper_2205_15346_amd", "csrc", "arnoldi.hip"),
+                                       "xxz_L20_csr_hbm_traffic.json")
+        if csr_traffic and csr_traffic.get("shape") == [8, 2, 4, 2, 1] and csr["roofline"]["kernel"] == "project":
+            csr["roofline"]["traffic"] = csr_traffic["project_bytes_per_launch"]
+        log(f"[bench] CSR storage ({csr['storage']}): {csr['ms_per_step']:.1f} ms per solve, "
+            f"{csr['roofline']['kernel']} at {csr['roofline']['achieved']:.0f} GB/s")
 
     kernel_gbs = {k: (v["bytes"] / v["seconds"] / 1e9 if v["seconds"] > 0 else None) for k, v in totals.items()}
     traffic = measured_traffic(os.path.join(ROOT, "paper_2205_15346_amd", "csrc", "arnoldi.hip"))
@@ -467,9 +550,10 @@ def main():
                                  "split_projection")]
     if traffic and traffic.get("shape") != shape:
         traffic = None  # the counters were taken on another kernel shape
-    dominant = max(totals, key=lambda k: totals[k]["seconds"])
-    dom = totals[dominant]
-    achieved = dom["bytes"] / dom["seconds"] / 1e9
+    roof = roofline_of(totals)
+    if traffic and roof["kernel"] == "project":
+        roof["traffic"] = traffic["project_bytes_per_launch"]
+    roof["storage"] = H.storage
     alg_bytes = sum(v["bytes"] for v in totals.values())
     kernel_seconds = sum(v["seconds"] for v in totals.values())
 
@@ -482,6 +566,11 @@ def main():
         serving = bench_serving(te, torch, dev, args.serve_requests, args.serve_qps, wl.m, args.serve_budget_gb,
                                 sweep, args.serve_sweep_requests, bool(args.serve_saturation) or args.serve_qps <= 0)
     paper = bench_paper_model(te, torch, dev, packed_only=args.paper_model == 2) if args.paper_model else None
+    bose = None
+    if args.bose_solves > 0:
+        bose = bench_workload(te, torch, dev, "bose_K12", args.bose_solves, 1)
+        log(f"[bench] bose_K12: {bose['ms_per_step']:.1f} ms per solve, {bose['restarts_per_solve']} restarts, "
+            f"{bose['roofline']['kernel']} at {bose['roofline']['achieved']:.0f} GB/s ({bose['storage']})")
 
     cpu = None
     if args.cpu_restarts > 0:
@@ -504,26 +593,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "dim": wl.H.dim, "nnz": wl.H.nnz, "t": wl.t, "tol": wl.tol, "m": wl.m,
                    "seed": workloads.WORKLOADS[wl.name]["seed"]},
-        "roofline": {
-            "bound": "hbm",
-            "kernel": dominant,
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic["project_bytes_per_launch"] if (traffic and dominant == "project") else None,
-            "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "algorithmic_bytes_per_launch": dom["bytes"] / max(dom["launches"], 1),
-        },
+        "roofline": roof,
         "cpu_baseline": {k: v for k, v in cpu.items() if k != "seconds_per_solve"} if cpu else None,
         "hbm_gbs_algorithmic_all_kernels": alg_bytes / kernel_seconds / 1e9,
-        "spmv_orthogonalisation": {
-            "kernels": ["project", "fold", "update"],
-            "gbs": sum(totals[k]["bytes"] for k in ("project", "fold", "update"))
-            / sum(totals[k]["seconds"] for k in ("project", "fold", "update")) / 1e9,
-            "frac_of_peak": sum(totals[k]["bytes"] for k in ("project", "fold", "update"))
-            / sum(totals[k]["seconds"] for k in ("project", "fold", "update")) / 1e9 / HBM_PEAK_GBS,
-        },
+        "spmv_orthogonalisation": spmv_orth_rates(totals, wl.H.dim, wl.H.nnz, wl.m, restarts * args.steps),
         "hbm_gbs_algorithmic_wall": alg_bytes / elapsed / 1e9,
         "kernel_gbs": kernel_gbs,
         "kernel_ms_per_solve": {k: 1e3 * v["seconds"] / args.steps for k, v in totals.items()},
@@ -538,6 +611,7 @@ def main():
         "batch": batch,
         "serving": serving,
         "paper_model": paper,
+        "bose_K12": bose,
     }
     print(json.dumps(line), flush=True)
 
