@@ -279,13 +279,13 @@ def bench_batch(te, torch, dev, n_instances, m, profile):
     return rec
 
 
-def serve_engine(te, torch, hs, reqs, v0, m, budget_gb, arrivals, label):
+def serve_engine(te, torch, hs, reqs, v0, m, budget_gb, arrivals, label, lane_rows=0, lane_jobs=0):
     """Submit reqs at the given arrival times (seconds from the start) into a threaded engine;
     returns per-request (submitted, finished, info, result) and the engine stats."""
     small = min(hs.values(), key=lambda h: h.dim)
     vw = torch.zeros(small.dim, dtype=torch.complex128, device=v0[0].device)
     vw[0] = 1.0
-    with te.Engine(int(budget_gb * 1e9), m=m, max_jobs=256) as eng:
+    with te.Engine(int(budget_gb * 1e9), m=m, max_jobs=256, lane_rows=lane_rows, lane_jobs=lane_jobs) as eng:
         w = eng.submit(small, vw, 1.0, 1e-8)  # warm-up (kernels, tuning)
         eng.wait(w, timeout=600)
         torch.cuda.synchronize()
@@ -318,7 +318,7 @@ def latency_summary(lat):
 
 
 def bench_serving(te, torch, dev, n_requests, qps, m, budget_gb, sweep=(), sweep_requests=48,
-                  saturation=False):
+                  saturation=False, saturation_requests=0, lane_rows=0, lane_jobs=0):
     """Poisson arrivals of XXZ (L 14..22) and Bose (K=N 10..12) requests into the threaded engine
     (continuous batching, admission by footprint), against the same stream served one request at a
     time by te_evolve (FIFO: completion = max(arrival, previous completion) + measured solve time).
@@ -365,7 +365,8 @@ def bench_serving(te, torch, dev, n_requests, qps, m, budget_gb, sweep=(), sweep
     def run(n, q, label):
         reqs = base[:n]
         arrivals = [0.0] * n if q is None else [r.arrival / q for r in reqs]
-        infos, outs, st = serve_engine(te, torch, hs, reqs, v0[:n], m, budget_gb, arrivals, label)
+        infos, outs, st = serve_engine(te, torch, hs, reqs, v0[:n], m, budget_gb, arrivals, label, lane_rows,
+                                       lane_jobs)
         first = min(i.submitted for i, _ in infos)
         last = max(i.finished for i, _ in infos)
         lat = [i.finished - i.submitted for i, _ in infos]
@@ -385,11 +386,12 @@ def bench_serving(te, torch, dev, n_requests, qps, m, budget_gb, sweep=(), sweep
             f"p99 {rec['one_at_a_time_fifo']['latency_ms']['p99'] / 1e3:.3f} s")
         return rec
 
-    out = {"m": m, "hbm_budget_gb": budget_gb,
+    out = {"m": m, "hbm_budget_gb": budget_gb, "lane_rows": lane_rows, "lane_jobs": lane_jobs,
            "mean_service_ms": 1e3 * sum(service[:n_requests]) / n_requests,
            "one_at_a_time_saturation_states_per_s": n_requests / sum(service[:n_requests])}
     if saturation:
-        sat = run(n_requests, None, "saturation (all requests at t=0)")
+        n_sat = saturation_requests or n_requests
+        sat = run(n_sat, None, f"saturation ({n_sat} requests at t=0)")
         out["saturation"] = sat
         if qps <= 0:
             qps = 0.7 * sat["states_per_s"]
@@ -474,10 +476,15 @@ def main():
                     help="also time the solve with the matrix kept as CSR instead of packed (0: skip)")
     ap.add_argument("--batch-instances", type=int, default=256, help="instances of the XXZ batch (0: skip)")
     ap.add_argument("--batch-profile", type=int, default=1, help="also run the batch in profiling mode")
-    ap.add_argument("--serve-requests", type=int, default=16, help="requests of the serving run (0: skip)")
-    ap.add_argument("--serve-qps", type=float, default=2.0, help="arrival rate; <= 0: 70%% of the saturation rate")
+    ap.add_argument("--serve-requests", type=int, default=120, help="requests of the serving run (0: skip)")
+    ap.add_argument("--serve-qps", type=float, default=0.0, help="arrival rate; <= 0: 70%% of the saturation rate")
     ap.add_argument("--serve-budget-gb", type=float, default=96.0)
     ap.add_argument("--serve-saturation", type=int, default=0, help="first measure saturation (all arrive at 0)")
+    ap.add_argument("--serve-saturation-requests", type=int, default=60,
+                    help="requests of the saturation run (0: as many as the serving run)")
+    ap.add_argument("--serve-lane-rows", type=int, default=1 << 20,
+                    help="engine lanes: jobs of at least this many rows in a lane of their own (0: one lane)")
+    ap.add_argument("--serve-lane-jobs", type=int, default=2, help="resident jobs of the large-job lane")
     ap.add_argument("--serve-sweep", default="", help="comma-separated QPS values for a sweep")
     ap.add_argument("--serve-sweep-requests", type=int, default=48)
     ap.add_argument("--paper-model", type=int, default=2,
@@ -564,7 +571,8 @@ def main():
     if args.serve_requests > 0:
         sweep = [float(x) for x in args.serve_sweep.split(",") if x.strip()]
         serving = bench_serving(te, torch, dev, args.serve_requests, args.serve_qps, wl.m, args.serve_budget_gb,
-                                sweep, args.serve_sweep_requests, bool(args.serve_saturation) or args.serve_qps <= 0)
+                                sweep, args.serve_sweep_requests, bool(args.serve_saturation) or args.serve_qps <= 0,
+                                args.serve_saturation_requests, args.serve_lane_rows, args.serve_lane_jobs)
     paper = bench_paper_model(te, torch, dev, packed_only=args.paper_model == 2) if args.paper_model else None
     bose = None
     if args.bose_solves > 0:

@@ -422,6 +422,16 @@ te_status te_step_search(int32_t k, const double* alpha, const double* beta, dou
  * state stay resident across restarts.  A job's arithmetic does not depend on the other jobs
  * of a round: with one kernel shape its result is bitwise the same alone and in any mix.
  *
+ * Lanes (te_engine_config.lane_rows > 0).  Every job of a round advances by one restart, so a
+ * job whose restarts are cheap but many (a small matrix, a long time, a tight tolerance) moves
+ * at the pace of the largest job beside it.  With two lanes, jobs of at least lane_rows rows
+ * run in a lane of their own, at most lane_jobs at a time in submission order, on a second
+ * stream, while the smaller jobs go round in the other lane at their own pace; the device runs
+ * both lanes' kernels side by side.  Job ids stay one sequence over both lanes; the statistics
+ * add up both lanes (busy_seconds: the larger of the two; tuning: the small-job lane's).  The
+ * lanes run side by side only with TE_ENGINE_THREADED (otherwise te_engine_wait drives one lane,
+ * then the other).
+ *
  * Job buffers: v0 and v_out are device pointers of dim complex owned by the caller; v0 must
  * hold its data when te_engine_submit is called and stay unchanged until the job is admitted,
  * v_out must stay valid until the job is done (it is complete once te_engine_poll reports
@@ -446,6 +456,12 @@ typedef struct {
     int32_t update_rows_per_thread; /* update and recombination: 1 or 2; 0 = 2 */
     uint32_t flags;                 /* TE_ENGINE_* */
     te_options opt;                 /* step-size / quadrature options; opt.flags: 0 or TE_OPT_LANCZOS3 */
+    int64_t lane_rows;              /* 0: one lane.  > 0: two lanes, each an engine of its own (own
+                                       stream, rounds and half of hbm_budget) running concurrently:
+                                       jobs of at least lane_rows rows go to the large-job lane,
+                                       which keeps at most lane_jobs of them resident (admitted in
+                                       submission order), the others to the small-job lane */
+    int32_t lane_jobs;              /* resident jobs of the large-job lane, 1..max_jobs (0 = 2) */
 } te_engine_config;
 
 enum { TE_JOB_QUEUED = 0, TE_JOB_RUNNING = 1, TE_JOB_DONE = 2, TE_JOB_FAILED = 3 };

@@ -169,6 +169,10 @@ struct te_engine_s {
     std::condition_variable cv_work, cv_done;
     std::thread worker;
     bool stop = false;
+    // two lanes (cfg.lane_rows > 0): this engine only routes; lane[0] takes jobs below lane_rows
+    // rows, lane[1] the others; route[id] = (lane, id in that lane)
+    te_engine_s* lane[2] = {nullptr, nullptr};
+    std::vector<std::pair<int, te_job>> route;
 
     ~te_engine_s();
 };
@@ -742,12 +746,15 @@ te_status check_config(const te_engine_config& c) {
     if (c.flags & ~(TE_ENGINE_THREADED | TE_ENGINE_PROFILE)) return set_error(TE_ERR_INVALID_ARG, "unknown flags");
     if (c.opt.flags & ~TE_OPT_LANCZOS3)
         return set_error(TE_ERR_INVALID_ARG, "engine options take only TE_OPT_LANCZOS3 (profiling: TE_ENGINE_PROFILE)");
+    if (c.lane_rows < 0 || c.lane_jobs < 0 || c.lane_jobs > c.max_jobs)
+        return set_error(TE_ERR_INVALID_ARG, "lane_rows must be >= 0 and lane_jobs within 0..max_jobs");
     return check_options(c.opt);
 }
 
 }  // namespace
 
 te_engine_s::~te_engine_s() {
+    for (auto* l : lane) delete l;
     for (auto& p : plans) {
         p.release_graph();
         if (p.last_use) (void)hipEventDestroy(p.last_use);
@@ -794,6 +801,26 @@ te_status te_engine_create(te_engine* out, const te_engine_config* cfg, void* st
     te_status rc = check_config(*cfg);
     if (rc != TE_OK) return rc;
     if (cfg->hbm_budget < PoolAlloc::kAlign) return set_error(TE_ERR_INVALID_ARG, "hbm_budget too small");
+    if (cfg->lane_rows > 0) {  // two lanes: a router over two engines, each with half the budget
+        auto* r = new (std::nothrow) te_engine_s();
+        if (!r) return set_error(TE_ERR_OUT_OF_MEMORY, "host allocation failed");
+        r->cfg = *cfg;
+        te_engine_config c = *cfg;
+        c.lane_rows = 0;
+        c.lane_jobs = 0;
+        c.hbm_budget = cfg->hbm_budget / 2 / PoolAlloc::kAlign * PoolAlloc::kAlign;
+        rc = te_engine_create(&r->lane[0], &c, stream);  // small jobs: the caller's stream, if any
+        if (rc == TE_OK) {
+            c.max_jobs = cfg->lane_jobs ? cfg->lane_jobs : std::min(2, cfg->max_jobs);
+            rc = te_engine_create(&r->lane[1], &c, nullptr);  // large jobs: a stream of its own
+        }
+        if (rc != TE_OK) {
+            delete r;
+            return rc;
+        }
+        *out = r;
+        return TE_OK;
+    }
     auto* e = new (std::nothrow) te_engine_s();
     if (!e) return set_error(TE_ERR_OUT_OF_MEMORY, "host allocation failed");
     e->cfg = *cfg;
@@ -866,6 +893,16 @@ te_status te_engine_create(te_engine* out, const te_engine_config* cfg, void* st
 te_status te_engine_submit(te_engine e, te_hamiltonian h, const te_c128* v0, te_c128* v_out, double t, double tol,
                            te_job* id) {
     if (!e || !h || !v0 || !v_out) return set_error(TE_ERR_INVALID_ARG, "null pointer");
+    if (e->lane[0]) {
+        const int l = (int64_t)h->csr.dim >= e->cfg.lane_rows ? 1 : 0;
+        std::lock_guard<std::mutex> lk(e->mu);  // ids in submission order over both lanes
+        te_job local = -1;
+        te_status rc = te_engine_submit(e->lane[l], h, v0, v_out, t, tol, &local);
+        if (rc != TE_OK) return rc;
+        e->route.emplace_back(l, local);
+        if (id) *id = (te_job)e->route.size() - 1;
+        return TE_OK;
+    }
     if (!std::isfinite(t) || t < 0.0) return set_error(TE_ERR_INVALID_ARG, "t must be finite and >= 0");
     if (!std::isfinite(tol) || !(tol > 0.0)) return set_error(TE_ERR_INVALID_ARG, "tol must be finite and > 0");
     const int dim = h->csr.dim;
@@ -905,8 +942,23 @@ te_status te_engine_submit(te_engine e, te_hamiltonian h, const te_c128* v0, te_
     return TE_OK;
 }
 
+// the lane and the lane's id of a routed job
+static bool routed(te_engine e, te_job id, te_engine* l, te_job* local) {
+    std::lock_guard<std::mutex> lk(e->mu);
+    if (id < 0 || id >= (te_job)e->route.size()) return false;
+    *l = e->lane[e->route[(size_t)id].first];
+    *local = e->route[(size_t)id].second;
+    return true;
+}
+
 te_status te_engine_poll(te_engine e, te_job id, te_job_info* info, te_result* res) {
     if (!e) return set_error(TE_ERR_INVALID_ARG, "null engine");
+    if (e->lane[0]) {
+        te_engine l;
+        te_job local;
+        if (!routed(e, id, &l, &local)) return set_error(TE_ERR_INVALID_ARG, "unknown job id");
+        return te_engine_poll(l, local, info, res);
+    }
     std::lock_guard<std::mutex> lk(e->mu);
     if (id < 0 || id >= (te_job)e->jobs.size()) return set_error(TE_ERR_INVALID_ARG, "unknown job id");
     const JobRec& j = e->jobs[(size_t)id];
@@ -930,6 +982,20 @@ te_status te_engine_poll(te_engine e, te_job id, te_job_info* info, te_result* r
 te_status te_engine_wait(te_engine e, te_job id, double timeout_s) {
     if (!e) return set_error(TE_ERR_INVALID_ARG, "null engine");
     const double deadline = timeout_s < 0.0 ? 1e300 : now_s() + timeout_s;
+    if (e->lane[0]) {
+        if (id == -1) {
+            for (te_engine l : e->lane) {
+                const double left = timeout_s < 0.0 ? -1.0 : std::max(0.0, deadline - now_s());
+                te_status rc = te_engine_wait(l, -1, left);
+                if (rc != TE_OK) return rc;
+            }
+            return TE_OK;
+        }
+        te_engine l;
+        te_job local;
+        if (!routed(e, id, &l, &local)) return set_error(TE_ERR_INVALID_ARG, "unknown job id");
+        return te_engine_wait(l, local, timeout_s);
+    }
     std::unique_lock<std::mutex> lk(e->mu);
     if (id >= (te_job)e->jobs.size() || id < -1) return set_error(TE_ERR_INVALID_ARG, "unknown job id");
     const bool threaded = (e->cfg.flags & TE_ENGINE_THREADED) != 0;
@@ -950,6 +1016,30 @@ te_status te_engine_wait(te_engine e, te_job id, double timeout_s) {
 
 te_status te_engine_get_stats(te_engine e, te_engine_stats* out) {
     if (!e || !out) return set_error(TE_ERR_INVALID_ARG, "null pointer");
+    if (e->lane[0]) {
+        te_engine_stats a, b;
+        te_status rc = te_engine_get_stats(e->lane[0], &a);
+        if (rc == TE_OK) rc = te_engine_get_stats(e->lane[1], &b);
+        if (rc != TE_OK) return rc;
+        *out = a;
+        out->rounds += b.rounds;
+        out->plans += b.plans;
+        out->jobs_submitted += b.jobs_submitted;
+        out->jobs_done += b.jobs_done;
+        out->jobs_failed += b.jobs_failed;
+        out->jobs_queued += b.jobs_queued;
+        out->jobs_running += b.jobs_running;
+        out->pool_bytes += b.pool_bytes;
+        out->pool_used += b.pool_used;
+        out->pool_peak += b.pool_peak;
+        out->busy_seconds = std::max(a.busy_seconds, b.busy_seconds);
+        for (int k = 0; k < TE_KERNEL_CLASSES; ++k) {
+            out->prof.launches[k] += b.prof.launches[k];
+            out->prof.seconds[k] += b.prof.seconds[k];
+            out->prof.bytes[k] += b.prof.bytes[k];
+        }
+        return TE_OK;
+    }
     std::lock_guard<std::mutex> lk(e->mu);
     std::memset(out, 0, sizeof(*out));
     out->rounds = e->observed;
@@ -970,6 +1060,16 @@ te_status te_engine_get_stats(te_engine e, te_engine_stats* out) {
 
 te_status te_engine_destroy(te_engine e) {
     if (!e) return set_error(TE_ERR_INVALID_ARG, "null engine");
+    if (e->lane[0]) {
+        te_status rc = TE_OK;
+        for (te_engine& l : e->lane) {
+            const te_status r = te_engine_destroy(l);
+            if (rc == TE_OK) rc = r;
+            l = nullptr;
+        }
+        delete e;
+        return rc;
+    }
     {
         std::lock_guard<std::mutex> lk(e->mu);
         e->stop = true;
@@ -1005,6 +1105,8 @@ te_status te_batch_create(te_batch* out, const te_engine_config* cfg, void* stre
     *out = nullptr;
     te_engine_config c = *cfg;
     c.flags &= ~TE_ENGINE_THREADED;
+    c.lane_rows = 0;  // a batch runs as one lane
+    c.lane_jobs = 0;
     if (c.max_jobs == 0) c.max_jobs = 1;
     c.hbm_budget = 0;
     te_status rc = check_config(c);

@@ -95,7 +95,8 @@ class te_engine_config(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int32), ("max_jobs", ctypes.c_int32), ("hbm_budget", ctypes.c_uint64),
                 ("lanes_per_row", ctypes.c_int32), ("nnz_per_lane", ctypes.c_int32),
                 ("rows_per_thread", ctypes.c_int32), ("update_rows_per_thread", ctypes.c_int32),
-                ("flags", ctypes.c_uint32), ("opt", te_options)]
+                ("flags", ctypes.c_uint32), ("opt", te_options), ("lane_rows", ctypes.c_int64),
+                ("lane_jobs", ctypes.c_int32)]
 
 
 class te_job_info(ctypes.Structure):
@@ -592,10 +593,12 @@ class Engine:
     until it is done; `submit` returns the job id."""
 
     def __init__(self, hbm_budget, m=40, max_jobs=1024, shape=None, update_rows_per_thread=0, threaded=True,
-                 profile=False, options=None, stream=None, rows_per_thread=0):
+                 profile=False, options=None, stream=None, rows_per_thread=0, lane_rows=0, lane_jobs=0):
         flags = (TE_ENGINE_THREADED if threaded else 0) | (TE_ENGINE_PROFILE if profile else 0)
         cfg = _engine_config(m, max_jobs, hbm_budget, shape, update_rows_per_thread, flags, options,
                              rows_per_thread)
+        cfg.lane_rows = int(lane_rows)
+        cfg.lane_jobs = int(lane_jobs)
         self._e = _P()
         st = ctypes.c_void_p(0) if stream is None else _stream(stream)
         _check(_lib.te_engine_create(ctypes.byref(self._e), ctypes.byref(cfg), st))

@@ -60,6 +60,7 @@ def test_default_config():
     assert (c.m, c.max_jobs, c.hbm_budget, c.lanes_per_row, c.nnz_per_lane, c.rows_per_thread,
             c.update_rows_per_thread, c.flags) == (40, 1024, 0, 0, 0, 0, 0, te.TE_ENGINE_THREADED)
     assert c.opt.n_substeps == 10 and c.opt.shrink == 0.97
+    assert (c.lane_rows, c.lane_jobs) == (0, 0)  # one lane unless asked
 
 
 @pytest.mark.parametrize("field,value,status", [
@@ -67,7 +68,8 @@ def test_default_config():
     ("max_jobs", 16385, "TE_ERR_INVALID_ARG"), ("lanes_per_row", 3, "TE_ERR_INVALID_ARG"),
     ("update_rows_per_thread", 3, "TE_ERR_INVALID_ARG"), ("rows_per_thread", 3, "TE_ERR_INVALID_ARG"),
     ("flags", 8, "TE_ERR_INVALID_ARG"),
-    ("hbm_budget", 0, "TE_ERR_INVALID_ARG")])
+    ("hbm_budget", 0, "TE_ERR_INVALID_ARG"), ("lane_rows", -1, "TE_ERR_INVALID_ARG"),
+    ("lane_jobs", -1, "TE_ERR_INVALID_ARG"), ("lane_jobs", 1025, "TE_ERR_INVALID_ARG")])
 def test_engine_create_validates_before_touching_the_device(field, value, status):
     from paper_2205_15346_amd import te
     c = te.te_engine_default_config(hbm_budget=1 << 30)

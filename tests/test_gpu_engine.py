@@ -160,6 +160,41 @@ def test_engine_alone_and_in_the_mix():
             assert st.pool_peak <= budget and st.jobs_done == 6 and st.plans >= 2
 
 
+@pytest.mark.parametrize("threaded", [True, False])
+def test_engine_two_lanes(threaded):
+    """Two lanes: jobs of at least lane_rows rows run in their own lane (at most lane_jobs
+    resident, in submission order), the others beside them; every result is bitwise its solo
+    te_evolve run, ids follow submission order over both lanes, statistics add up."""
+    te = lib()
+    HL, vL = W.xxz_chain(13, 61, n_v0=3)   # 8192 rows: the large-job lane
+    HS, vS = W.xxz_chain(10, 62, n_v0=2)   # 1024 rows: the small-job lane
+    HB, vB = W.bosonic_chain(6, 6, seed=63)  # 462 rows
+    budget = 2 * 4 * te.te_job_footprint(8192, M)
+    with hamiltonian(HL) as hL, hamiltonian(HS) as hS, hamiltonian(HB) as hB:
+        reqs = [(hL, vL[0], 20.0, 1e-8), (hS, vS[0], 40.0, 1e-10), (hL, vL[1], 5.0, 1e-8),
+                (hB, vB, 30.0, 1e-10), (hL, vL[2], 10.0, 1e-6), (hS, vS[1], 3.0, 1e-8)]
+        dev = [to_dev(v) for _, v, _, _ in reqs]
+        announce(f"engine: two lanes, threaded={threaded}")
+        with te.Engine(budget, m=M, max_jobs=8, threaded=threaded, lane_rows=4096, lane_jobs=1, **TUNE) as eng:
+            ids = [eng.submit(h, d, t, tol) for (h, _, t, tol), d in zip(reqs, dev)]
+            assert ids == list(range(len(reqs)))
+            eng.wait(-1, timeout=300)
+            infos = [eng.poll(j) for j in ids]
+            assert all(i.state == te.TE_JOB_DONE for i, _ in infos)
+            for (h, _, t, tol), d, j, (info, res) in zip(reqs, dev, ids, infos):
+                ref, rres = alone(h, d, t, tol)
+                assert bool((eng.output(j) == ref).all())
+                assert same_result(res, rres)
+            # the large-job lane keeps one job at a time, in submission order
+            big = [infos[k][0] for k in (0, 2, 4)]
+            assert big[0].finished <= big[1].admitted and big[1].finished <= big[2].admitted
+            st = eng.stats()
+            assert st.jobs_submitted == st.jobs_done == len(reqs) and st.jobs_running == 0
+            assert st.pool_bytes <= budget
+            with pytest.raises(te.TEError):
+                eng.poll(len(reqs))
+
+
 def test_engine_admission_by_footprint():
     te = lib()
     H, vs = W.xxz_chain(12, 41, n_v0=5)
