@@ -471,6 +471,9 @@ def main():
     ap.add_argument("--shape", default="1,8,4,2,0",
                     help="projection kernel shape lanes,nnz,rows,update_rows,split for the single solve "
                          "(default: the shape te_autotune selects for this matrix on MI355X), or 'auto'")
+    ap.add_argument("--storage", choices=["packed", "csr"], default="packed",
+                    help="matrix storage of the timed solves: packed entries where the matrix allows "
+                         "(default), or the CSR as given")
     ap.add_argument("--three-term", type=int, default=1, help="also time the three-term mode (0: skip)")
     ap.add_argument("--csr-storage", type=int, default=1,
                     help="also time the solve with the matrix kept as CSR instead of packed (0: skip)")
@@ -510,7 +513,7 @@ def main():
     torch.cuda.set_device(dev)
     wl = workloads.workload(args.workload)
     log(f"[bench] workload {wl.name}: d={wl.H.dim} nnz={wl.H.nnz} t={wl.t} tol={wl.tol} m={wl.m}")
-    H = te.te_hamiltonian_create(wl.H.row_ptr, wl.H.col, wl.H.val)
+    H = te.te_hamiltonian_create(wl.H.row_ptr, wl.H.col, wl.H.val, store_csr=args.storage == "csr")
     v0 = torch.from_numpy(wl.v0).to(dev)
     out = torch.empty_like(v0)
     plain = te.te_default_options()
@@ -552,7 +555,8 @@ def main():
             f"{csr['roofline']['kernel']} at {csr['roofline']['achieved']:.0f} GB/s")
 
     kernel_gbs = {k: (v["bytes"] / v["seconds"] / 1e9 if v["seconds"] > 0 else None) for k, v in totals.items()}
-    traffic = measured_traffic(os.path.join(ROOT, "paper_2205_15346_amd", "csrc", "arnoldi.hip"))
+    traffic = measured_traffic(os.path.join(ROOT, "paper_2205_15346_amd", "csrc", "arnoldi.hip"),
+                               f"{wl.name}_{'csr_' if args.storage == 'csr' else ''}hbm_traffic.json")
     shape = [tuning[k] for k in ("lanes_per_row", "nnz_per_lane", "rows_per_thread", "update_rows_per_thread",
                                  "split_projection")]
     if traffic and traffic.get("shape") != shape:
@@ -600,6 +604,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": wl.name, "dim": wl.H.dim, "nnz": wl.H.nnz, "t": wl.t, "tol": wl.tol, "m": wl.m,
+                   "storage": H.storage,
                    "seed": workloads.WORKLOADS[wl.name]["seed"]},
         "roofline": roof,
         "cpu_baseline": {k: v for k, v in cpu.items() if k != "seconds_per_solve"} if cpu else None,
