@@ -206,7 +206,7 @@ def bench_three_term(te, torch, H, v0, out, wl, steps):
     }
 
 
-def bench_batch(te, torch, dev, n_instances, m, profile):
+def bench_batch(te, torch, dev, n_instances, m, profile, reference=True):
     """The 256-instance XXZ batch (L ~ U{10..18}, 1-8 vectors each, t ~ U[1,100], tol in
     {1e-6, 1e-8, 1e-10}) through te_batch_*, against the same jobs one at a time through
     te_evolve.  Latency of a job = time from the start of the run to its result."""
@@ -243,7 +243,7 @@ def bench_batch(te, torch, dev, n_instances, m, profile):
     torch.cuda.synchronize()
     s0 = time.perf_counter()
     k = 0
-    for gi, (h, vs, t, tol) in enumerate(groups):
+    for gi, (h, vs, t, tol) in enumerate(groups if reference else []):
         for vi, v in enumerate(vs):
             out, res = te.te_evolve(h, v, t, tol, m)
             seq_done.append(time.perf_counter() - s0)
@@ -254,7 +254,9 @@ def bench_batch(te, torch, dev, n_instances, m, profile):
             worst = max(worst, float((out - outs[gi][vi]).norm()) / max(allowed, 1e-300))
             k += 1
     seq_s = time.perf_counter() - s0
-    log(f"[bench] one at a time: {seq_s:.2f} s, {n_jobs / seq_s:.1f} states/s")
+    if reference:
+        log(f"[bench] one at a time: {seq_s:.2f} s, {n_jobs / seq_s:.1f} states/s")
+
     for g in groups:
         g[0].destroy()
     rec = {
@@ -263,13 +265,14 @@ def bench_batch(te, torch, dev, n_instances, m, profile):
         "states_per_s": n_jobs / batch_s, "seconds": batch_s,
         "latency_ms": {"p50": 1e3 * percentile(lat, 50), "p99": 1e3 * percentile(lat, 99)},
         "one_at_a_time": {"states_per_s": n_jobs / seq_s, "seconds": seq_s,
-                          "latency_ms": {"p50": 1e3 * percentile(seq_done, 50), "p99": 1e3 * percentile(seq_done, 99)}},
-        "speedup_vs_one_at_a_time": seq_s / batch_s,
+                          "latency_ms": {"p50": 1e3 * percentile(seq_done, 50), "p99": 1e3 * percentile(seq_done, 99)}}
+        if reference else None,
+        "speedup_vs_one_at_a_time": seq_s / batch_s if reference else None,
         "rounds": stats.rounds, "plans": stats.plans, "failed": failed,
         "pool_peak_gb": stats.pool_peak / 1e9,
         "shape": {"lanes_per_row": stats.tuning.lanes_per_row, "nnz_per_lane": stats.tuning.nnz_per_lane,
                   "update_rows_per_thread": stats.tuning.update_rows_per_thread},
-        "max_diff_over_bounds_and_roundoff_vs_one_at_a_time": worst,
+        "max_diff_over_bounds_and_roundoff_vs_one_at_a_time": worst if reference else None,
     }
     if prof:
         rec["profile"] = {"kernel_gbs": kernel_rates(prof),
@@ -479,6 +482,8 @@ def main():
                     help="also time the solve with the matrix kept as CSR instead of packed (0: skip)")
     ap.add_argument("--batch-instances", type=int, default=256, help="instances of the XXZ batch (0: skip)")
     ap.add_argument("--batch-profile", type=int, default=1, help="also run the batch in profiling mode")
+    ap.add_argument("--batch-reference", type=int, default=1,
+                    help="also run the batch's jobs one at a time (0: skip; for kernel profiles of the batch)")
     ap.add_argument("--serve-requests", type=int, default=120, help="requests of the serving run (0: skip)")
     ap.add_argument("--serve-qps", type=float, default=0.0, help="arrival rate; <= 0: 70%% of the saturation rate")
     ap.add_argument("--serve-budget-gb", type=float, default=96.0)
@@ -571,7 +576,8 @@ def main():
     H.destroy()
     batch = serving = None
     if args.batch_instances > 0:
-        batch = bench_batch(te, torch, dev, args.batch_instances, wl.m, bool(args.batch_profile))
+        batch = bench_batch(te, torch, dev, args.batch_instances, wl.m, bool(args.batch_profile),
+                            bool(args.batch_reference))
     if args.serve_requests > 0:
         sweep = [float(x) for x in args.serve_sweep.split(",") if x.strip()]
         serving = bench_serving(te, torch, dev, args.serve_requests, args.serve_qps, wl.m, args.serve_budget_gb,

@@ -754,7 +754,8 @@ te_status check_config(const te_engine_config& c) {
 }  // namespace
 
 te_engine_s::~te_engine_s() {
-    for (auto* l : lane) delete l;
+    for (auto* l : lane)
+        if (l) (void)te_engine_destroy(l);  // stops the lane's scheduler thread first
     for (auto& p : plans) {
         p.release_graph();
         if (p.last_use) (void)hipEventDestroy(p.last_use);
