@@ -350,8 +350,9 @@ typedef struct {
     double project_us;              /* measured time of one projection launch, 0 if not measured */
 } te_tuning;
 
-/* Times every supported projection shape for Krylov dimension m and keeps the fastest in h
- * (out may be NULL).  Synchronous. */
+/* Times every supported projection shape for Krylov dimension m, then the update kernel with one
+ * and two rows per thread in the chosen shape, and keeps the fastest in h (out may be NULL).
+ * Synchronous. */
 te_status te_autotune(te_hamiltonian h, int32_t m, te_tuning* out, void* stream);
 te_status te_get_tuning(te_hamiltonian h, te_tuning* out); /* the shape te_evolve will use */
 te_status te_set_tuning(te_hamiltonian h, const te_tuning* t); /* TE_ERR_INVALID_ARG if unsupported */

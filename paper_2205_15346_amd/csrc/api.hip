@@ -392,7 +392,8 @@ void tune_cache_store(const std::string& key, const te_tuning& t) {
     std::fclose(f);
 }
 
-// Times the projection kernel (iteration j = m/2, zero basis) for every supported shape.
+// Times the projection kernel (iteration j = m/2, zero basis) for every supported shape, then
+// the update kernel with one and two rows per thread.
 te_status run_autotune(te_hamiltonian h, Workspace* w, hipStream_t s) {
     const std::string key = tune_key(h, w->m);
     te_tuning best{};
@@ -433,6 +434,31 @@ te_status run_autotune(te_hamiltonian h, Workspace* w, hipStream_t s) {
                 best_us = us;
                 best = te_tuning{sh[0], sh[1], rp, rpt_u, sp, us};
             }
+        }
+    }
+    // Rows per thread of the update (and recombination), timed at the same iteration.  The
+    // squared norm of column J is set to 1 so that the update streams its columns instead of
+    // taking the breakdown exit (its results in the workspace are not used).
+    const double2 one = make_double2(1.0, 0.0);
+    if (err == hipSuccess) err = hipMemcpyAsync(&w->rb.red[2 * J + 1], &one, sizeof(one), hipMemcpyHostToDevice, s);
+    if (err == hipSuccess) err = hipStreamSynchronize(s);  // `one` lives on this stack frame
+    double best_u = 1e30;
+    for (int ru = 1; ru <= 2 && err == hipSuccess; ++ru) {
+        const Tiling t = make_tiling(w->dim, best.rows_per_thread, best.lanes_per_row, best.nnz_per_lane, ru,
+                                     best.split_projection);
+        RedBuf rb = w->rb;
+        rb.n_tiles = t.n_tiles_p;
+        rb.n_norm = t.n_tiles_u;
+        err = launch_update(t, w->V, w->ld, w->dim, J, w->y, w->st, rb, s);
+        if (err == hipSuccess) err = hipEventRecord(e0, s);
+        for (int q = 0; q < 3 && err == hipSuccess; ++q) err = launch_update(t, w->V, w->ld, w->dim, J, w->y, w->st, rb, s);
+        if (err == hipSuccess) err = hipEventRecord(e1, s);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        if (err == hipSuccess && 1e3 * ms / 3.0 < best_u) {
+            best_u = 1e3 * ms / 3.0;
+            best.update_rows_per_thread = ru;
         }
     }
     (void)hipEventDestroy(e0);
