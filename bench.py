@@ -10,7 +10,12 @@ inputs already resident in device memory.  Prints ONE JSON line on stdout.
 
 The timed solves run in profiling mode (an event around every kernel), which yields the
 per-kernel durations for the roofline entry; the same count of solves is also timed in the
-default graph mode and reported as "graph_mode" (not the headline value).
+default graph mode and reported as "graph_mode" (not the headline value).  The same line
+carries informational entries: the three-term mode, the solve with the matrix kept as complex
+CSR ("csr_storage", with its own roofline), the Bose chain K = N = 12 at m = 60 ("bose_K12"),
+the paper's own example ("paper_model"), the 256-instance batch against the same jobs one at a
+time ("batch"), serving with Poisson arrivals at 70% of the measured saturation against a FIFO
+server of single solves ("serving"), and the CPU oracle on a bounded sample ("cpu_baseline").
 """
 
 import argparse

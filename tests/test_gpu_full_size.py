@@ -103,3 +103,47 @@ def test_xxz_L20_krylov_basis_orthogonal(xxz_L20):
     scale = wl.H.norm1()
     assert np.linalg.norm(R[:, :-1]) <= 10 * k * EPS * scale
     assert abs(np.linalg.norm(R[:, -1]) - beta[-1]) <= 10 * k * EPS * scale
+
+
+@pytest.fixture(scope="module")
+def bose_K12():
+    announce("building bose_K12 inputs and loading the oracle's state")
+    wl = W.workload("bose_K12")
+    v_or, meta, mk = oracle_state("bose_K12")
+    assert mk.input_digest(wl.H, wl.v0) == meta["input_sha256"], "inputs differ from those the oracle ran on"
+    assert (meta["t"], meta["tol"], meta["m"]) == (wl.t, wl.tol, wl.m)
+    return wl, v_or, meta
+
+
+# the Bose chain packs to 2-byte codes; the shape the autotuner picks for it (two lanes per row,
+# split projection, one update row per thread), a neighbour of it and the one-row-per-thread
+# fused shape; complex CSR in its CSR shape
+BOSE_CASES = [("packed", (2, 8, 4, 1, 1)), ("packed", (2, 8, 2, 2, 1)), ("packed", (1, 8, 4, 2, 0)),
+              ("csr", (8, 2, 4, 2, 1))]
+
+
+@pytest.mark.parametrize("storage,shape", BOSE_CASES)
+def test_bose_K12_matches_oracle_state(bose_K12, storage, shape):
+    """The Bose chain K = N = 12 (d = 1,352,078; m = 60, t = 50, tol = 1e-10): the m = 60 path
+    at full size against the oracle's state."""
+    te = lib()
+    wl, v_or, meta = bose_K12
+    announce(f"bose_K12 vs oracle state: storage={storage} shape={shape}")
+    h = te.te_hamiltonian_create(wl.H.row_ptr, wl.H.col, wl.H.val, store_csr=(storage == "csr"))
+    try:
+        assert h.storage == ("packed16" if storage == "packed" else "complex")
+        te.te_set_tuning(h, *shape)
+        v, res = te.te_evolve(h, to_dev(wl.v0), wl.t, wl.tol, wl.m)
+        v = to_host(v)
+    finally:
+        h.destroy()
+    gap = float(np.linalg.norm(v - v_or))
+    announce(f"  |gpu - oracle| = {gap:.3e}, restarts {res.steps} vs {meta['steps']}, "
+             f"bound {res.err_bound:.6e} vs {meta['err_bound']:.6e}")
+    assert res.t_reached == wl.t
+    assert gap <= 2 * wl.tol + 1e-12
+    assert res.err_bound <= wl.tol
+    assert abs(res.steps - meta["steps"]) <= 1
+    assert res.matvecs == wl.m * res.steps
+    # particle number is conserved by construction (the basis has N bosons); the norm by unitarity
+    assert abs(np.linalg.norm(v) - 1.0) <= res.err_bound + 1e-12
