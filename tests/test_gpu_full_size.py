@@ -34,6 +34,8 @@ def _maker():
 def oracle_state(name):
     mk = _maker()
     npy, meta_path = mk.state_paths(name)
+    if not (os.path.exists(npy) and os.path.exists(meta_path)):
+        pytest.skip(f"no stored oracle state for {name}: run tests/golden/make_oracle_states.py {name}")
     with open(meta_path) as f:
         meta = json.load(f)
     v = np.load(npy, allow_pickle=False)
