@@ -2,6 +2,8 @@
 
 from dataclasses import dataclass
 
+import math
+
 import numpy as np
 
 
@@ -59,6 +61,11 @@ def from_triplets(dim: int, rows: np.ndarray, cols: np.ndarray, vals: np.ndarray
 
 
 def random_state(rng: np.random.Generator, dim: int) -> np.ndarray:
-    """Complex standard-normal vector, normalised to unit 2-norm."""
+    """Complex standard-normal vector, normalised to unit 2-norm.
+
+    The squared norm is summed by NumPy's own pairwise summation (no BLAS call), so the vector is
+    the same bits for every BLAS thread count (a threaded BLAS dot product sums in an order that
+    depends on the number of threads)."""
     v = rng.standard_normal(dim) + 1j * rng.standard_normal(dim)
-    return v / np.linalg.norm(v)
+    nrm = math.sqrt(float(np.sum(v.real * v.real)) + float(np.sum(v.imag * v.imag)))
+    return v / nrm
