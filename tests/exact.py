@@ -4,12 +4,25 @@ These are test helpers (not the oracle): they compute exp(-iHt) v through numpy.
 the textbook route, so the oracle's Krylov result can be pinned against them.
 """
 
+import hashlib
+
 import numpy as np
+
+_EIGH = {}  # digest of a dense matrix -> its eigendecomposition (the last few matrices)
+
+
+def _eigh(A):
+    key = hashlib.sha1(np.ascontiguousarray(A).tobytes()).hexdigest()
+    if key not in _EIGH:
+        if len(_EIGH) >= 4:
+            _EIGH.pop(next(iter(_EIGH)))
+        _EIGH[key] = np.linalg.eigh(A)
+    return _EIGH[key]
 
 
 def dense_evolve(H, v0, t):
     A = H.to_scipy().toarray() if hasattr(H, "to_scipy") else np.asarray(H)
-    lam, U = np.linalg.eigh(A)
+    lam, U = _eigh(A)
     return U @ (np.exp(-1j * lam * t) * (U.conj().T @ v0))
 
 
