@@ -174,11 +174,19 @@ def bench_workload(te, torch, dev, name, steps, warmup, shape="auto", store_csr=
         te.te_set_tuning(H, *shape)
     r = time_solves(te, torch, H, v0, out, wl, steps, warmup, name)
     res = r["res"]
+    tuning = te.te_get_tuning(H).as_dict()
+    roof = roofline_of(r["totals"])
+    traffic = measured_traffic(os.path.join(ROOT, "paper_2205_15346_amd", "csrc", "arnoldi.hip"),
+                               f"{name}_{'csr_' if store_csr else ''}hbm_traffic.json")
+    shape_now = [tuning[k] for k in ("lanes_per_row", "nnz_per_lane", "rows_per_thread", "update_rows_per_thread",
+                                     "split_projection")]
+    if traffic and traffic.get("shape") == shape_now and roof["kernel"] == "project":
+        roof["traffic"] = traffic["project_bytes_per_launch"]
     rec = {"workload": name, "dim": wl.H.dim, "nnz": wl.H.nnz, "t": wl.t, "tol": wl.tol, "m": wl.m,
-           "storage": H.storage, "kernel_shape": te.te_get_tuning(H).as_dict(),
+           "storage": H.storage, "kernel_shape": tuning,
            "value": steps / r["elapsed"], "unit": "states/s", "ms_per_step": 1e3 * r["elapsed"] / steps,
            "restarts_per_solve": res.steps, "matvecs_per_solve": res.matvecs, "err_bound": res.err_bound,
-           "warnings": res.warnings, "roofline": roofline_of(r["totals"]),
+           "warnings": res.warnings, "roofline": roof,
            "spmv_orthogonalisation": spmv_orth_rates(r["totals"], wl.H.dim, wl.H.nnz, wl.m, res.steps * steps),
            "kernel_ms_per_solve": {k: 1e3 * v["seconds"] / steps for k, v in r["totals"].items()}}
     H.destroy()

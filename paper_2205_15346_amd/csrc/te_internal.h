@@ -260,9 +260,9 @@ inline double csr_entries_bytes(const Csr& c) {
 // by the autotuner: g lanes share a row of the sparse product, each keeping u nonzeros in
 // flight, and every thread owns rpt_p rows of the dense passes.
 struct Tiling {
-    int rpt_p;      // rows per thread, projection kernel (1 or 2)
-    int g;          // lanes per row in the sparse product (4 or 8)
-    int u;          // nonzeros per lane in flight (1, 2 or 4)
+    int rpt_p;      // rows per thread, projection kernel (1, 2 or 4)
+    int g;          // lanes per row in the sparse product (1, 2, 4 or 8)
+    int u;          // nonzeros per lane in flight (g = 1: 8 or 16; 2: 8; 4: 1 or 4; 8: 2)
     int n_tiles_p;  // tiles (workgroups) of the projection kernel
     int rpt_u;      // rows per thread, update and recombination kernels (1 or 2)
     int n_tiles_u;
