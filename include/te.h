@@ -458,11 +458,14 @@ typedef struct {
     uint32_t flags;                 /* TE_ENGINE_* */
     te_options opt;                 /* step-size / quadrature options; opt.flags: 0 or TE_OPT_LANCZOS3 */
     int64_t lane_rows;              /* 0: one lane.  > 0: two lanes, each an engine of its own (own
-                                       stream, rounds and half of hbm_budget) running concurrently:
-                                       jobs of at least lane_rows rows go to the large-job lane,
-                                       which keeps at most lane_jobs of them resident (admitted in
-                                       submission order), the others to the small-job lane */
-    int32_t lane_jobs;              /* resident jobs of the large-job lane, 1..max_jobs (0 = 2) */
+                                       rounds and half of hbm_budget; the small-job lane on the
+                                       given stream, the large-job lane on a stream of its own)
+                                       running concurrently: jobs of at least lane_rows rows go to
+                                       the large-job lane, which keeps at most lane_jobs of them
+                                       resident (admitted in submission order), the others to the
+                                       small-job lane.  A job must fit half of hbm_budget. */
+    int32_t lane_jobs;              /* resident jobs of the large-job lane, 1..max_jobs (0: two, or
+                                       max_jobs if that is smaller) */
 } te_engine_config;
 
 enum { TE_JOB_QUEUED = 0, TE_JOB_RUNNING = 1, TE_JOB_DONE = 2, TE_JOB_FAILED = 3 };
