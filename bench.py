@@ -599,7 +599,9 @@ def main():
     paper = bench_paper_model(te, torch, dev, packed_only=args.paper_model == 2) if args.paper_model else None
     bose = None
     if args.bose_solves > 0:
-        bose = bench_workload(te, torch, dev, "bose_K12", args.bose_solves, 1)
+        # the shape the autotuner picks on this matrix in most runs (its neighbours are within 2%),
+        # pinned so that every run times the same kernels and the counter record applies
+        bose = bench_workload(te, torch, dev, "bose_K12", args.bose_solves, 1, shape=(2, 8, 4, 1, 1))
         log(f"[bench] bose_K12: {bose['ms_per_step']:.1f} ms per solve, {bose['restarts_per_solve']} restarts, "
             f"{bose['roofline']['kernel']} at {bose['roofline']['achieved']:.0f} GB/s ({bose['storage']})")
 
