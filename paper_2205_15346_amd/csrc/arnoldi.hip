@@ -190,6 +190,13 @@ __device__ __forceinline__ double2 entry_zero<double2>() { return make_double2(0
 template <>
 __device__ __forceinline__ double entry_zero<double>() { return 0.0; }
 
+// The build of this restart is over at iteration j (finished, or broken down before j): both
+// fields are loaded before either is tested, so the test costs one round trip.
+__device__ __forceinline__ bool build_over(const DevState* __restrict__ st, int j) {
+    const int done = st->done, limit = st->k_limit;
+    return (done != 0) | (j >= limit);
+}
+
 // Sources of a row's stored entries: (column, value) of entry k.  CSR keeps both per entry;
 // packed entries keep a code into a table of (column offset, value) pairs and, for the
 // diagonal, the row's real diagonal (the sum runs over the same entries in the same order, so
@@ -354,12 +361,14 @@ __device__ __forceinline__ void tile_spmv_p8_rows(const int* __restrict__ rp, co
     }
 }
 
-// Whole block.  A table of 1-byte codes (at most 256 pairs) is staged in LDS first.
+// Whole block; false (and nothing computed) when the build is over at iteration j.  A table of
+// 1-byte codes (at most 256 pairs) is staged in LDS first, while the state is tested.
 template <int G, int U>
-__device__ __forceinline__ void tile_spmv(const int* __restrict__ rp, const int* __restrict__ ci,
+__device__ __forceinline__ bool tile_spmv(const int* __restrict__ rp, const int* __restrict__ ci,
                                           const double2* __restrict__ val, const double* __restrict__ rval,
                                           const Packed& pk, const double2* __restrict__ x, int r0, int r1,
-                                          double2* __restrict__ y, double2* ytile) {
+                                          double2* __restrict__ y, double2* ytile, const DevState* __restrict__ st,
+                                          int j) {
     if (pk.c8) {
         __shared__ int s_toff[256];
         __shared__ double2 s_tval[256];
@@ -367,6 +376,7 @@ __device__ __forceinline__ void tile_spmv(const int* __restrict__ rp, const int*
             s_toff[i] = pk.toff[i];
             s_tval[i] = pk.tval[i];
         }
+        if (build_over(st, j)) return false;  // the same for every thread of the block
         __syncthreads();
         if (pk.col)
             tile_spmv_t<G, U>(rp, PackSrc<uint8_t, true>{pk.c8, pk.col, pk.slice, s_toff, s_tval, pk.diag, pk.dcode},
@@ -376,9 +386,11 @@ __device__ __forceinline__ void tile_spmv(const int* __restrict__ rp, const int*
         else
             tile_spmv_t<G, U>(rp, PackSrc<uint8_t, false>{pk.c8, nullptr, nullptr, s_toff, s_tval, pk.diag, pk.dcode},
                               x, r0, r1, y, ytile);
-        return;
+        return true;
     }
+    if (build_over(st, j)) return false;
     with_entries(ci, val, rval, pk, [&](const auto& src) { tile_spmv_t<G, U>(rp, src, x, r0, r1, y, ytile); });
+    return true;
 }
 
 // Projection of iteration j on one tile.  FROM_Y: the sparse product already ran (k_yspmv)
@@ -392,14 +404,15 @@ __device__ __forceinline__ void project_body(const int* __restrict__ rp, const i
     constexpr int R = kBlock * RPT;
     __shared__ double2 ytile[FROM_Y ? 1 : R];
     __shared__ double2 wpart[kWaves][kMaxVals];
-    if (st->done || j >= st->k_limit) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r0 = tile * R;
     const int r1 = min(r0 + R, dim);
     const double2* __restrict__ x = V + (int64_t)j * ld;
 
-    if (!FROM_Y) {
-        tile_spmv<G, U>(rp, ci, val, rval, pk, x, r0, r1, y, ytile);
+    if (FROM_Y) {
+        if (build_over(st, j)) return;
+    } else {
+        if (!tile_spmv<G, U>(rp, ci, val, rval, pk, x, r0, r1, y, ytile, st, j)) return;
         __syncthreads();
     }
     // Rows past the end of a ragged tile read row r1 - 1 and are weighted by zero, so the loads
@@ -482,9 +495,8 @@ __global__ __launch_bounds__(kBlock) void k_yspmv(const int* __restrict__ rp, co
                                                    const double2* __restrict__ val, const double* __restrict__ rval,
                                                    Packed pk, const double2* __restrict__ V, int64_t ld, int dim,
                                                    int j, double2* __restrict__ y, const DevState* __restrict__ st) {
-    if (st->done || j >= st->k_limit) return;
     const int r0 = blockIdx.x * kBlock * RPT;
-    tile_spmv<G, U>(rp, ci, val, rval, pk, V + (int64_t)j * ld, r0, min(r0 + kBlock * RPT, dim), y, nullptr);
+    tile_spmv<G, U>(rp, ci, val, rval, pk, V + (int64_t)j * ld, r0, min(r0 + kBlock * RPT, dim), y, nullptr, st, j);
 }
 
 // Batched projection.  Jobs that share H form a group; a group of one runs the fused kernel
@@ -627,7 +639,7 @@ __global__ __launch_bounds__(kBlock) void k_bdots(const JobView* __restrict__ jo
 // Folds value v of iteration j over all tiles in a fixed order (whole block).
 __device__ __forceinline__ void fold_value(const DevState* __restrict__ st, const RedBuf& rb, int j, int v) {
     __shared__ double lds[kWaves];
-    if (st->done || j >= st->k_limit) return;
+    if (build_over(st, j)) return;
     if (st->p.three_term && v < 2 * (j - 1)) return;  // columns the three-term recurrence skips
     double2 acc = make_double2(0.0, 0.0);
     for (int t = threadIdx.x; t < rb.n_tiles; t += kBlock) acc = cadd(acc, rb.part[(size_t)v * rb.n_tiles + t]);
@@ -660,8 +672,16 @@ __device__ __forceinline__ void update_body(double2* __restrict__ V, int64_t ld,
     __shared__ double2 cp[kMaxM + 1], g[kMaxM + 1], cs[kMaxM + 1];
     __shared__ double sj_sh;
     __shared__ int stop_sh;
-    if (st->done || j >= st->k_limit) return;
     const int tid = threadIdx.x;
+    const int r0 = tile * (kBlock * RPT);
+    // this tile's rows of y, loaded while the prologue below waits on the state
+    double2 yl[RPT];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int r = r0 + tid + q * kBlock;
+        yl[q] = (r < dim) ? load_stream(y + r) : make_double2(0.0, 0.0);  // last reader of y
+    }
+    if (build_over(st, j)) return;
     const bool rec = tile == 0;
     if (tid == 0) {
         int stop = 0;
@@ -762,14 +782,10 @@ __device__ __forceinline__ void update_body(double2* __restrict__ V, int64_t ld,
     }
     __syncthreads();
 
-    const int r0 = tile * (kBlock * RPT);
     const bool last = (j + 1) == st->p.m;
     double2 p[RPT];
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-        const int r = r0 + tid + q * kBlock;
-        p[q] = (r < dim) ? cscale(load_stream(y + r), sj) : make_double2(0.0, 0.0);  // last reader of y
-    }
+    for (int q = 0; q < RPT; ++q) p[q] = cscale(yl[q], sj);
     for (int i = i_lo; i <= j; ++i) {
         const double2 c = cs[i];
         const double2* __restrict__ vi = V + (int64_t)i * ld;
