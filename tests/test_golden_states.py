@@ -34,7 +34,7 @@ def _stored(name):
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("name", ["xxz_L20", "bose_K12"])
+@pytest.mark.parametrize("name", ["xxz_L20", "bose_K12", "paper_d1565904"])
 def test_stored_state_is_consistent(name):
     mk, v, meta = _stored(name)
     spec = W.WORKLOADS[name]

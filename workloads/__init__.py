@@ -12,10 +12,10 @@ from .csr import CSR, random_state
 from .xxz import xxz_chain, xxz_nnz
 from .bosonic import bose_chain_params, bosonic_chain, fock_basis, fock_dim, capped_fock_basis
 from .memory_burden import memory_burden_model, memory_burden_dim
-from .configs import workload, WORKLOADS, batch_jobs, serving_requests
+from .configs import PAPER_MODEL_PARAMS, workload, WORKLOADS, batch_jobs, serving_requests
 
 __all__ = [
     "CSR", "random_state", "xxz_chain", "xxz_nnz", "bosonic_chain", "bose_chain_params", "fock_basis",
     "fock_dim", "capped_fock_basis", "memory_burden_model", "memory_burden_dim",
-    "workload", "WORKLOADS", "batch_jobs", "serving_requests",
+    "PAPER_MODEL_PARAMS", "workload", "WORKLOADS", "batch_jobs", "serving_requests",
 ]

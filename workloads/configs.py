@@ -4,6 +4,10 @@ single solves (Hamiltonian, v0, t, tol, m):
   xxz_L12   XXZ ring L=12 (d=4,096, nnz=28,672), seed 1, t=10,  tol=1e-8,  m=40
   xxz_L20   XXZ ring L=20 (d=1,048,576, nnz=11,534,336), seed 2, t=100, tol=1e-8, m=40
   bose_K12  Bose chain K=N=12 (d=1,352,078), seed 3, t=50, tol=1e-10, m=60
+  paper_d1565904  the paper's performance example (Sec. "Analysis of Performance"): eq.
+            fullHamiltonianSimple with K=K'=10, N_m=5, N_0=N_c=100 (d=1,565,904, 122,109,504
+            stored entries), v0 of eq. initialStateSimple (no random draw: seed unused), t=10,
+            err_max=1e-7, m=40
 batch  (batch_jobs): 256 XXZ instances; master default_rng(4) draws per instance i, in
   this order, L=integers(10,19), n_v0=integers(1,9), t=uniform(1,100),
   tol=choice([1e-6,1e-8,1e-10]); the instance's H and its v0s come from seed 1000+i; m=40.
@@ -21,6 +25,7 @@ import numpy as np
 
 from .bosonic import bosonic_chain
 from .csr import random_state
+from .memory_burden import memory_burden_model
 from .xxz import xxz_chain
 
 
@@ -38,7 +43,11 @@ WORKLOADS = {
     "xxz_L12": dict(kind="xxz", size=12, seed=1, t=10.0, tol=1e-8, m=40),
     "xxz_L20": dict(kind="xxz", size=20, seed=2, t=100.0, tol=1e-8, m=40),
     "bose_K12": dict(kind="bose", size=12, seed=3, t=50.0, tol=1e-10, m=60),
+    "paper_d1565904": dict(kind="memory_burden", size=10, seed=0, t=10.0, tol=1e-7, m=40),
 }
+
+# the paper's example: K = K' = size, N_m = size / 2, N_0 = N_c = 100
+PAPER_MODEL_PARAMS = dict(K=10, Kp=10, Nm=5, N0=100, Nc=100.0)
 
 
 def build_hamiltonian(kind: str, size: int, seed: int, with_v0: bool = True):
@@ -46,6 +55,10 @@ def build_hamiltonian(kind: str, size: int, seed: int, with_v0: bool = True):
         return xxz_chain(size, seed, with_v0=with_v0)
     if kind == "bose":
         return bosonic_chain(size, size, seed, with_v0=with_v0)
+    if kind == "memory_burden":
+        params = dict(PAPER_MODEL_PARAMS, K=size, Kp=size, Nm=size // 2)
+        H, v0, _ = memory_burden_model(**params)
+        return H, (v0 if with_v0 else None)
     raise ValueError(kind)
 
 
