@@ -66,7 +66,9 @@ __device__ __forceinline__ double lane_get(double x, int i) {
 }
 
 // Implicit QL with Wilkinson shifts on the k x k symmetric tridiagonal (diagonal a, off-diagonal
-// b), run by wave 0: lane i holds d_i and e_i in registers, lane q owns row q of the eigenvector
+// b): the textbook method of Bowdler, Martin, Reinsch and Wilkinson (Numer. Math. 11, 1968; the
+// procedure EISPACK publishes as tql2), restructured for one wave.  Run by wave 0: lane i holds
+// d_i and e_i in registers, lane q owns row q of the eigenvector
 // matrix (Qt, transposed in LDS).  Within a sweep every d/e value read is a pre-sweep value, so
 // the reads sit off the rotation chain; deflation points come from one ballot.  On return lam[]
 // holds the eigenvalues (unsorted) and Qt[n * 64 + q] = Q[q][n].  False if an eigenvalue needed
