@@ -395,7 +395,12 @@ def bench_serving(te, torch, dev, n_requests, qps, m, budget_gb, sweep=(), sweep
                "one_at_a_time_fifo": {"states_per_s": f_rate, "latency_ms": latency_summary(f_lat)},
                "rounds": st.rounds, "plans": st.plans, "pool_peak_gb": st.pool_peak / 1e9,
                "failed": sum(1 for i, _ in infos if i.state != te.TE_JOB_DONE),
-               "max_diff_over_bounds_and_roundoff_vs_one_at_a_time": worst}
+               "max_diff_over_bounds_and_roundoff_vs_one_at_a_time": worst,
+               # the requests behind the tail: the three slowest in the engine
+               "slowest": [{"request": k, "kind": reqs[k].kind, "size": reqs[k].size, "t": reqs[k].t,
+                            "tol": reqs[k].tol, "latency_s": lat[k], "fifo_latency_s": f_lat[k],
+                            "solve_alone_s": service[k]}
+                           for k in sorted(range(n), key=lambda k: -lat[k])[:3]]}
         log(f"[bench] {label}: {rec['states_per_s']:.2f} states/s, p50 {rec['latency_ms']['p50'] / 1e3:.3f} s, "
             f"p99 {rec['latency_ms']['p99'] / 1e3:.3f} s | one at a time {f_rate:.2f} states/s, "
             f"p50 {rec['one_at_a_time_fifo']['latency_ms']['p50'] / 1e3:.3f} s, "
@@ -505,7 +510,8 @@ def main():
                     help="requests of the saturation run (0: as many as the serving run)")
     ap.add_argument("--serve-lane-rows", type=int, default=1 << 20,
                     help="engine lanes: jobs of at least this many rows in a lane of their own (0: one lane)")
-    ap.add_argument("--serve-lane-jobs", type=int, default=2, help="resident jobs of the large-job lane")
+    ap.add_argument("--serve-lane-jobs", type=int, default=3,
+                    help="resident jobs of the large-job lane (3: the lowest p99 at the default operating point)")
     ap.add_argument("--serve-sweep", default="", help="comma-separated QPS values for a sweep")
     ap.add_argument("--serve-sweep-requests", type=int, default=48)
     ap.add_argument("--paper-model", type=int, default=2,
