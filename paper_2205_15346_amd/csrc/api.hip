@@ -350,7 +350,8 @@ te_status retile(te_hamiltonian h, Workspace* w, const Tiling& t) {
 // "gfx950/<storage> dim nnz m": the best shape depends on how the entries are stored
 std::string tune_key(te_hamiltonian h, int m) {
     const Csr& c = h->csr;
-    const char* storage = c.pk.c8 ? (c.pk.col ? "coded8" : "packed8") : c.pk.c16 ? (c.pk.col ? "coded16" : "packed16")
+    const bool coded = c.pk.col || c.pk.col16;
+    const char* storage = c.pk.c8 ? (coded ? "coded8" : "packed8") : c.pk.c16 ? (coded ? "coded16" : "packed16")
                           : c.rval ? "real" : "complex";
     return std::string("gfx950/") + storage + " " + std::to_string(c.dim) + " " + std::to_string(c.nnz) + " " +
            std::to_string(m);
@@ -731,7 +732,8 @@ static te_status try_pack(te_hamiltonian h, hipStream_t s, bool* packed) {
         if (q == kDiag) q = (uint16_t)dcode;
     // value codes: codes and columns sliced in chunks of 64 rows (te::Packed)
     const int nch = (dim + 63) / 64;
-    std::vector<int> slice, scol;
+    std::vector<int> slice, scol, cbase;
+    std::vector<uint16_t> scol16;  // with cbase: the 16-bit form of scol
     if (!by_pairs) {
         std::vector<int> cols;
         std::vector<uint16_t> scode;
@@ -762,6 +764,43 @@ static te_status try_pack(te_hamiltonian h, hipStream_t s, bool* packed) {
             }
         }
         code.swap(scode);
+        // 16-bit columns when the entries q of every chunk of 64 rows (a group) lie within 65535
+        // columns of the group's smallest: a base per group, an offset per entry
+        try {
+            const int64_t groups = total / 64;
+            cbase.assign((size_t)groups, INT32_MAX);
+            std::vector<int> cmax((size_t)groups, -1);
+            for (int rr = 0; rr < dim; ++rr) {
+                const int64_t g0 = slice[(size_t)(rr >> 6)] / 64;
+                for (int k = rp[(size_t)rr]; k < rp[(size_t)rr + 1]; ++k) {
+                    const size_t g = (size_t)(g0 + (k - rp[(size_t)rr]));
+                    const int c = cols[(size_t)k];
+                    cbase[g] = std::min(cbase[g], c);
+                    cmax[g] = std::max(cmax[g], c);
+                }
+            }
+            bool fits = true;
+            for (size_t g = 0; g < cbase.size() && fits; ++g) {
+                if (cmax[g] < 0) cbase[g] = 0;  // no entry in the group (a chunk narrower than its slot count)
+                else fits = (int64_t)cmax[g] - cbase[g] <= 65535;
+            }
+            if (fits) {
+                scol16.assign((size_t)total, 0);
+                for (int rr = 0; rr < dim; ++rr) {
+                    const int64_t at = slice[(size_t)(rr >> 6)] + (rr & 63);
+                    const int64_t g0 = slice[(size_t)(rr >> 6)] / 64;
+                    for (int k = rp[(size_t)rr]; k < rp[(size_t)rr + 1]; ++k) {
+                        const int64_t q = k - rp[(size_t)rr];
+                        scol16[(size_t)(at + 64 * q)] = (uint16_t)(cols[(size_t)k] - cbase[(size_t)(g0 + q)]);
+                    }
+                }
+            } else {
+                cbase.clear();
+            }
+        } catch (...) {
+            cbase.clear();
+            scol16.clear();
+        }
     }
     const int64_t ncode = (int64_t)code.size();
     const bool narrow = dcode <= 255;
@@ -771,7 +810,11 @@ static te_status try_pack(te_hamiltonian h, hipStream_t s, bool* packed) {
     int* d_toff = (int*)dev_alloc(tab.off.size() * sizeof(int));
     double2* d_tval = (double2*)dev_alloc(tab.val.size() * sizeof(double2));
     double* d_diag = (double*)dev_alloc((size_t)dim * sizeof(double));
-    int* d_scol = by_pairs ? nullptr : (int*)dev_alloc(scol.size() * sizeof(int));
+    // value codes: the columns, 32-bit or (one buffer) the group bases followed by 16-bit offsets
+    const bool cols16 = !by_pairs && !scol16.empty();
+    const size_t col_bytes =
+        by_pairs ? 0 : cols16 ? cbase.size() * sizeof(int) + scol16.size() * sizeof(uint16_t) : scol.size() * sizeof(int);
+    int* d_scol = by_pairs ? nullptr : (int*)dev_alloc(col_bytes);
     int* d_slice = by_pairs ? nullptr : (int*)dev_alloc(slice.size() * sizeof(int));
     auto release = [&]() {
         dev_free(d_code);
@@ -797,8 +840,13 @@ static te_status try_pack(te_hamiltonian h, hipStream_t s, bool* packed) {
     if (e == hipSuccess) e = hipMemcpyAsync(d_toff, tab.off.data(), tab.off.size() * sizeof(int), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(d_tval, tab.val.data(), tab.val.size() * sizeof(double2), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(d_diag, diag.data(), (size_t)dim * sizeof(double), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess && !by_pairs)
+    if (e == hipSuccess && !by_pairs && !cols16)
         e = hipMemcpyAsync(d_scol, scol.data(), scol.size() * sizeof(int), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && cols16)
+        e = hipMemcpyAsync(d_scol, cbase.data(), cbase.size() * sizeof(int), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && cols16)
+        e = hipMemcpyAsync(d_scol + cbase.size(), scol16.data(), scol16.size() * sizeof(uint16_t),
+                           hipMemcpyHostToDevice, s);
     if (e == hipSuccess && !by_pairs)
         e = hipMemcpyAsync(d_slice, slice.data(), slice.size() * sizeof(int), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -814,14 +862,19 @@ static te_status try_pack(te_hamiltonian h, hipStream_t s, bool* packed) {
     Packed pk;
     if (narrow) pk.c8 = (const uint8_t*)d_code;
     else pk.c16 = (const uint16_t*)d_code;
-    pk.col = d_scol;  // value codes: the sliced columns
+    if (cols16) {  // value codes: the sliced columns as group bases + 16-bit offsets
+        pk.cbase = d_scol;
+        pk.col16 = (const uint16_t*)(d_scol + cbase.size());
+    } else {
+        pk.col = d_scol;  // value codes: the sliced columns
+    }
     pk.slice = d_slice;
     pk.toff = d_toff;
     pk.tval = d_tval;
     pk.diag = d_diag;
     pk.dcode = dcode;
     h->csr.pk = pk;
-    dev_free(h->col);  // CSR columns: dropped (pairs) or replaced by the sliced copy
+    dev_free(h->col);  // CSR columns: dropped (pairs) or replaced by the sliced copy (either form)
     h->col = d_scol;
     h->csr.col = nullptr;
     dev_free(h->val);
@@ -904,8 +957,9 @@ te_status te_hamiltonian_real_values(te_hamiltonian h, int32_t* real_values) {
 te_status te_hamiltonian_storage(te_hamiltonian h, int32_t* kind) {
     if (!h || !kind) return fail(TE_ERR_INVALID_ARG, "null pointer");
     const Packed& pk = h->csr.pk;
-    if (pk.c8) *kind = pk.col ? TE_STORAGE_CODED8 : TE_STORAGE_PACKED8;
-    else if (pk.c16) *kind = pk.col ? TE_STORAGE_CODED16 : TE_STORAGE_PACKED16;
+    const bool coded = pk.col || pk.col16;
+    if (pk.c8) *kind = coded ? TE_STORAGE_CODED8 : TE_STORAGE_PACKED8;
+    else if (pk.c16) *kind = coded ? TE_STORAGE_CODED16 : TE_STORAGE_PACKED16;
     else *kind = h->csr.rval ? TE_STORAGE_REAL : TE_STORAGE_COMPLEX;
     return TE_OK;
 }

@@ -213,13 +213,19 @@ struct CsrSrc {
     }
 };
 
-// COLS: value codes with explicit columns, both stored sliced (entry q of row r at
-// slice[r / 64] + 64 q + r % 64, so that the rows of a wave read consecutive addresses);
-// else codes of (column offset, value) pairs in CSR order.
-template <typename CT, bool COLS>
+// Columns of value codes, stored sliced like the codes (entry q of row r at slice[r / 64] +
+// 64 q + r % 64, so that the rows of a wave read consecutive addresses): kCols32 keeps every
+// column, kCols16 a 16-bit offset per entry from a base per group (the entries q of one chunk
+// of 64 rows: group slice[r / 64] / 64 + q).  kColsNone: codes of (column offset, value) pairs
+// in CSR order.
+enum { kColsNone = 0, kCols32 = 1, kCols16 = 2 };
+
+template <typename CT, int COLS>
 struct PackSrc {
     const CT* __restrict__ code;
     const int* __restrict__ cols;
+    const uint16_t* __restrict__ cols16;
+    const int* __restrict__ cbase;
     const int* __restrict__ slice;
     const int* __restrict__ toff;
     const double2* __restrict__ tval;
@@ -228,24 +234,31 @@ struct PackSrc {
     int r = 0;
     int at = 0;  // sliced: position of the row's first entry (entry k at at + 64 (k - kb))
     int kb = 0;
+    int cb = 0;  // kCols16: the chunk's first group
     double dg = 0.0;
     using V = double2;
     __device__ __forceinline__ PackSrc row(int rr, int kb_) const {
         PackSrc p = *this;
         p.r = rr;
         p.dg = diag[rr];
-        if constexpr (COLS) {
-            p.at = slice[rr >> 6] + (rr & 63);
+        if constexpr (COLS != kColsNone) {
+            const int s0 = slice[rr >> 6];
+            p.at = s0 + (rr & 63);
             p.kb = kb_;
+            if constexpr (COLS == kCols16) p.cb = s0 >> 6;
         }
         return p;
     }
     __device__ __forceinline__ void load(int k, int& c, double2& v) const {
         int q;
-        if constexpr (COLS) {
+        if constexpr (COLS == kCols32) {
             const int i = at + 64 * (k - kb);
             q = code[i];
             c = cols[i];
+        } else if constexpr (COLS == kCols16) {
+            const int i = at + 64 * (k - kb);
+            q = code[i];
+            c = cbase[cb + (k - kb)] + (int)cols16[i];
         } else {
             q = code[k];
             c = r + toff[q];
@@ -255,15 +268,28 @@ struct PackSrc {
     }
 };
 
+// the entry source of packed entries with the given code array and (pair or value) table
+template <typename CT, int COLS>
+__device__ __forceinline__ PackSrc<CT, COLS> pack_src(const CT* code, const Packed& pk, const int* toff,
+                                                      const double2* tval) {
+    return PackSrc<CT, COLS>{code, pk.col, pk.col16, pk.cbase, pk.slice, toff, tval, pk.diag, pk.dcode};
+}
+
+// Calls f with the packed source of the given codes, by how the columns are kept.
+template <typename CT, typename F>
+__device__ __forceinline__ void with_packed(const CT* code, const Packed& pk, const int* toff, const double2* tval,
+                                            F&& f) {
+    if (pk.col16) f(pack_src<CT, kCols16>(code, pk, toff, tval));
+    else if (pk.col) f(pack_src<CT, kCols32>(code, pk, toff, tval));
+    else f(pack_src<CT, kColsNone>(code, pk, toff, tval));
+}
+
 // Calls f with the source of the matrix's storage kind.
 template <typename F>
 __device__ __forceinline__ void with_entries(const int* ci, const double2* val, const double* rval, const Packed& pk,
                                              F&& f) {
-    if (pk.c8 && pk.col) f(PackSrc<uint8_t, true>{pk.c8, pk.col, pk.slice, pk.toff, pk.tval, pk.diag, pk.dcode});
-    else if (pk.c8) f(PackSrc<uint8_t, false>{pk.c8, nullptr, nullptr, pk.toff, pk.tval, pk.diag, pk.dcode});
-    else if (pk.c16 && pk.col)
-        f(PackSrc<uint16_t, true>{pk.c16, pk.col, pk.slice, pk.toff, pk.tval, pk.diag, pk.dcode});
-    else if (pk.c16) f(PackSrc<uint16_t, false>{pk.c16, nullptr, nullptr, pk.toff, pk.tval, pk.diag, pk.dcode});
+    if (pk.c8) with_packed(pk.c8, pk, pk.toff, pk.tval, f);
+    else if (pk.c16) with_packed(pk.c16, pk, pk.toff, pk.tval, f);
     else if (rval) f(CsrSrc<double>{ci, rval});
     else f(CsrSrc<double2>{ci, val});
 }
@@ -378,14 +404,14 @@ __device__ __forceinline__ bool tile_spmv(const int* __restrict__ rp, const int*
         }
         if (build_over(st, j)) return false;  // the same for every thread of the block
         __syncthreads();
-        if (pk.col)
-            tile_spmv_t<G, U>(rp, PackSrc<uint8_t, true>{pk.c8, pk.col, pk.slice, s_toff, s_tval, pk.diag, pk.dcode},
-                              x, r0, r1, y, ytile);
+        if (pk.col16)
+            tile_spmv_t<G, U>(rp, pack_src<uint8_t, kCols16>(pk.c8, pk, s_toff, s_tval), x, r0, r1, y, ytile);
+        else if (pk.col)
+            tile_spmv_t<G, U>(rp, pack_src<uint8_t, kCols32>(pk.c8, pk, s_toff, s_tval), x, r0, r1, y, ytile);
         else if constexpr (G == 1 && U % 4 == 0)
             tile_spmv_p8_rows<U, 1>(rp, pk.c8, s_toff, s_tval, pk.diag, pk.dcode, x, r0, r1, y, ytile);
         else
-            tile_spmv_t<G, U>(rp, PackSrc<uint8_t, false>{pk.c8, nullptr, nullptr, s_toff, s_tval, pk.diag, pk.dcode},
-                              x, r0, r1, y, ytile);
+            tile_spmv_t<G, U>(rp, pack_src<uint8_t, kColsNone>(pk.c8, pk, s_toff, s_tval), x, r0, r1, y, ytile);
         return true;
     }
     if (build_over(st, j)) return false;
@@ -612,13 +638,8 @@ __global__ __launch_bounds__(kBlock) void k_gspmm(const JobView* __restrict__ jo
             s_tval[i] = pk.tval[i];
         }
         __syncthreads();
-        if (pk.col)
-            group_spmv<G, U, NV>(gv, PackSrc<uint8_t, true>{pk.c8, pk.col, pk.slice, s_toff, s_tval, pk.diag, pk.dcode},
-                                 r0, r1, mask, xs, ys, nullptr);
-        else
-            group_spmv<G, U, NV>(gv,
-                                 PackSrc<uint8_t, false>{pk.c8, nullptr, nullptr, s_toff, s_tval, pk.diag, pk.dcode},
-                                 r0, r1, mask, xs, ys, nullptr);
+        with_packed(pk.c8, pk, s_toff, s_tval,
+                    [&](const auto& src) { group_spmv<G, U, NV>(gv, src, r0, r1, mask, xs, ys, nullptr); });
         return;
     }
     with_entries(gv.ci, gv.val, gv.rval, pk, [&](const auto& src) {

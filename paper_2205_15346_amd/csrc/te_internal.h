@@ -92,8 +92,10 @@ struct RedBuf {
 struct Packed {
     const uint8_t* c8 = nullptr;    // 1-byte codes, or
     const uint16_t* c16 = nullptr;  // 2-byte codes (at most one is set)
-    const int* col = nullptr;       // value codes: the columns (sliced); else unset
-    const int* slice = nullptr;     // value codes: [ceil(dim / 64)] chunk offsets
+    const int* col = nullptr;       // value codes: the columns (sliced), or
+    const uint16_t* col16 = nullptr;  // value codes: column - cbase[group] (sliced), with
+    const int* cbase = nullptr;     //   one base per group (chunk of 64 rows, entry position)
+    const int* slice = nullptr;     // value codes: [ceil(dim / 64)] chunk offsets (multiples of 64)
     const int* toff = nullptr;      // [dcode + 1] column offsets, toff[dcode] = 0
     const double2* tval = nullptr;  // [dcode + 1] values
     const double* diag = nullptr;   // [dim] real diagonal (0 where a row has none)
@@ -250,7 +252,8 @@ inline bool is_packed(const Packed& p) { return p.c8 != nullptr || p.c16 != null
 // real diagonal per row
 inline double csr_entries_bytes(const Csr& c) {
     const double nnz = (double)c.nnz, d = (double)c.dim;
-    const double cols = c.pk.col ? 4.0 * nnz : 0.0;  // the sliced padding is not counted
+    // the sliced padding and the 16-bit form's bases (one per 64 entry slots) are not counted
+    const double cols = c.pk.col ? 4.0 * nnz : c.pk.col16 ? 2.0 * nnz : 0.0;
     if (c.pk.c8) return 1.0 * nnz + cols + 8.0 * d;
     if (c.pk.c16) return 2.0 * nnz + cols + 8.0 * d;
     return (c.rval ? 12.0 : 20.0) * nnz;

@@ -278,3 +278,42 @@ def test_batch_mixes_storage_kinds():
     ro = O.evolve(H, vs[1], 6.0, 1e-8, 40)
     assert np.linalg.norm(to_host(outs[0][1]) - ro.v) <= 2e-8 + 1e-12
     destroy(hp, hr, hc, hz)
+
+
+def column_bytes_per_entry(te, h_coded, h_csr, H, x, shape):
+    """Bytes per entry the library's byte model charges the value-coded columns, from the
+    projection bytes of the same evolution on the coded and the complex-CSR handle: per launch
+    the coded matrix moves (1 + c) nnz + 8 d bytes where the CSR moves 20 nnz."""
+    prof = te.te_default_options(flags=te.TE_OPT_PROFILE)
+    got = []
+    for h in (h_coded, h_csr):
+        te.te_set_tuning(h, *shape)
+        v, res = te.te_evolve(h, x, 0.5, 1e-8, 20, options=prof)
+        p = te.te_last_profile(h).as_dict()["project"]
+        got.append((p["bytes"], p["launches"], to_host(v), res.steps))
+    (b0, n0, v0, s0), (b1, n1, v1, s1) = got
+    assert n0 == n1 and s0 == s1 and np.array_equal(v0, v1)  # same launches, bitwise the same result
+    return ((b0 - b1) / n0 - 8.0 * H.dim + 19.0 * H.nnz) / H.nnz
+
+
+@pytest.mark.parametrize("shape", [(1, 8, 4, 2, 1), (1, 8, 4, 2, 0)])
+def test_value_code_columns_16_and_32_bit(shape):
+    """Value codes keep each column as a 16-bit offset from a base per group (the entries q of a
+    chunk of 64 rows) when every group spans at most 65535 columns, else as 32 bits.  Both forms
+    expand back to the uploaded CSR and evolve bitwise like it."""
+    announce(f"value-code columns, 16 and 32 bit, shape {shape}")
+    te = lib()
+    # narrow: 3000 rows, every group within 3000 columns
+    N = few_values_hermitian(3000, 0.01, 5, 40)
+    # wide: 70000 rows with random columns, groups spanning nearly the whole range
+    Wd = few_values_hermitian(70000, 5e-5, 7, 40)
+    for H, want in ((N, 2.0), (Wd, 4.0)):
+        hc = te.te_hamiltonian_create(H.row_ptr, H.col, H.val)
+        hx = te.te_hamiltonian_create(H.row_ptr, H.col, H.val, store_csr=True, store_complex=True)
+        try:
+            assert hc.storage == "coded8" and hx.storage == "complex"
+            assert roundtrip(te, hc, H)
+            v0 = W.random_state(np.random.default_rng(11), H.dim)
+            assert column_bytes_per_entry(te, hc, hx, H, to_dev(v0), shape) == pytest.approx(want, abs=1e-9)
+        finally:
+            destroy(hc, hx)
